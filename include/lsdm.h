@@ -1,0 +1,185 @@
+/*
+ * lsdm.h - C ABI of the MI355X (gfx950) library for the hot path of the LNV
+ * linear-scaling density-matrix method: atom-blocked sparse products truncated
+ * to spherical interatomic ranges, the McWeeny/LNV density matrix
+ * K = 3LSL - 2LSLSL, the energy E = 2 Tr(KH) and its gradient dE/dL.
+ *
+ * Source of the operations: Bowler & Miyazaki, "Calculations on millions of
+ * atoms with DFT: linear scaling shows its potential", section 2 (Methodology):
+ *   - eq. 1 and eq. 2 index matrices by (atom, support function), so every
+ *     matrix here is a set of dense atom blocks of size nfn_i x nfn_j;
+ *   - the range cutoff on L stated after eq. 3 (an element is zero when the
+ *     interatomic distance exceeds the range) defines a range pattern;
+ *   - item 1 of the list of computational operations is the sparse matrix
+ *     multiplication (the example K_ij = L_ik S_kl L_lj);
+ *   - eq. 3 defines K from L and S; the electron-count constraint
+ *     N_e = 2 Tr(KS) fixes the spin factor 2 used in E = 2 Tr(KH).
+ *
+ * Conventions shared by every call
+ *   Units: positions and ranges in bohr (any consistent length unit works).
+ *   Periodicity: `lattice` holds three row vectors (9 doubles, row-major) or is
+ *     NULL for an open system.  Periodic matrices are image-resolved: a block
+ *     is keyed (i, j, n), n an integer translation applied to atom j, so ranges
+ *     larger than half the cell are exact (no folding).
+ *   Range test: a pair is in a pattern of range R iff
+ *     |x_j + n.T - x_i|^2 <= R^2 in IEEE double (a pair exactly at R is kept).
+ *   Value layout ("block layout"): the blocks of a pattern in row order, each
+ *     row sorted by (j, n0, n1, n2); block b is nfn_i x nfn_j row-major and
+ *     starts at val_off[b] (exported by lsdm_pattern_export).  Value arrays
+ *     passed to the library are DEVICE pointers to doubles in this layout.
+ *   Ownership: handles are created and destroyed by the library; value
+ *     buffers belong to the caller and are never freed by the library.  Device
+ *     workspace is allocated by the library (hipMalloc) when a handle is
+ *     created and released when it is destroyed.
+ *   Streams: compute calls enqueue work on `stream` (a hipStream_t, NULL = the
+ *     default stream) and return without waiting.  Only *_create calls
+ *     synchronise (they read sizes back).  Calls on one handle must not run
+ *     concurrently on different streams.
+ *   Errors: every call returns LSDM_OK (0) or a negative status; no exception
+ *     crosses the ABI; lsdm_last_error() returns a message for the calling
+ *     thread's last failure.  A failed call leaves its outputs undefined and
+ *     its handles valid.
+ */
+#ifndef LSDM_H
+#define LSDM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lsdm_system lsdm_system;
+typedef struct lsdm_pattern lsdm_pattern;
+typedef struct lsdm_plan lsdm_plan;
+typedef struct lsdm_lnv lsdm_lnv;
+
+enum {
+  LSDM_OK = 0,
+  LSDM_EINVAL = -1,        /* bad argument (NULL, NaN position, range < 0, nfn out of 1..16, ...) */
+  LSDM_EPATTERN = -2,      /* patterns of different systems combined */
+  LSDM_ENOMEM = -3,        /* device or host allocation failed, or a size limit was exceeded */
+  LSDM_EDEVICE = -4,       /* a HIP call failed */
+  LSDM_EUNSUPPORTED = -5   /* valid request the library does not implement */
+};
+
+/* Precision of the block products.  Traces, energies and K assembly are FP64
+ * in every mode. */
+enum {
+  LSDM_FP64 = 0,    /* FP64 inputs, FP64 MFMA, FP64 accumulation */
+  LSDM_FP32 = 1,    /* inputs rounded to FP32, FP32 MFMA, FP32 accumulation */
+  LSDM_BF16 = 2,    /* inputs rounded to BF16, BF16 MFMA, FP32 accumulation */
+  LSDM_FP32_RC = 3  /* FP32 products of the off-site parts plus FP64 on-site
+                       (block-diagonal) terms, see lsdm_multiply */
+};
+
+/* ---- system ------------------------------------------------------------ */
+/* Atoms with orbital blocks (eq. 1: support functions i-alpha on atom i).
+ * xyz: host, 3*n_atoms doubles.  nfn: host, n_atoms values in 1..16.
+ * lattice: host, 9 doubles (rows are the translation vectors) or NULL.
+ * Positions must be finite; periodic positions may lie outside the cell.
+ * Errors: LSDM_EINVAL. */
+int lsdm_system_create(int32_t n_atoms, const double* xyz, const int32_t* nfn,
+                       const double* lattice, lsdm_system** out);
+void lsdm_system_destroy(lsdm_system* sys);
+
+/* ---- range patterns (symbolic pass, step 1) ----------------------------- */
+/* Pattern of all blocks (i, j, n) within `range` (the locality cutoff stated
+ * after eq. 3), found by a cell-list neighbour search on the host, then laid
+ * out in the internal strip layout on the device.
+ * Errors: LSDM_EINVAL (range < 0 or not finite), LSDM_ENOMEM (the pattern
+ * would exceed the device or an index limit), LSDM_EDEVICE. */
+int lsdm_pattern_create(const lsdm_system* sys, double range, lsdm_pattern** out);
+/* Number of blocks and of values (doubles) of the block layout. */
+int lsdm_pattern_info(const lsdm_pattern* p, int64_t* n_blocks, int64_t* n_values);
+/* Copy the pattern to HOST arrays: row_ptr[n_atoms+1], col[n_blocks],
+ * img3[3*n_blocks], val_off[n_blocks].  Any output pointer may be NULL. */
+int lsdm_pattern_export(const lsdm_pattern* p, int64_t* row_ptr, int32_t* col,
+                        int32_t* img3, int64_t* val_off);
+void lsdm_pattern_destroy(lsdm_pattern* p);
+
+/* ---- truncated products (symbolic pass step 2 and the product) ---------- */
+/* Plan for C = P_C(op(A) op(B)): the exact product of op(A) and op(B)
+ * projected on C's pattern (C's range is the truncation), op = transpose when
+ * the flag is 1.  A transposed operand uses A's pattern mirrored
+ * ((i,j,n) -> (j,i,-n)).  The plan holds the task list of block triples
+ * (i,k,j) grouped into tiles and steps for the GPU kernels; it is built on the
+ * host (multithreaded) and kept on the device.
+ * Errors: LSDM_EPATTERN (patterns of different systems), LSDM_ENOMEM. */
+int lsdm_plan_create(const lsdm_pattern* A, int transA, const lsdm_pattern* B, int transB,
+                     const lsdm_pattern* C, lsdm_plan** out);
+/* n_triples: block triples (i,k,j) with (i,k) in op(A), (k,j) in op(B) and
+ * (i,j) in C (the useful work); flops: sum over triples of 2 nfn_i nfn_k nfn_j;
+ * plan_bytes: device memory held by the plan. */
+int lsdm_plan_info(const lsdm_plan* plan, int64_t* n_triples, double* flops, int64_t* plan_bytes);
+void lsdm_plan_destroy(lsdm_plan* plan);
+
+/* C = alpha P_C(op(A) op(B)) + beta C, values in block layout on device.
+ * dA, dB, dC: device doubles on the patterns given to lsdm_plan_create.
+ * prec: LSDM_FP64, LSDM_FP32, LSDM_BF16 or LSDM_FP32_RC.  In FP32_RC mode each
+ * operand is split into its on-site blocks D (i = j, n = 0) and the rest R, and
+ * AB = D_A B + A D_B - D_A D_B (FP64, block-diagonal scalings) + R_A R_B (FP32).
+ * dC must not alias dA or dB.  Errors: LSDM_EINVAL, LSDM_EDEVICE. */
+int lsdm_multiply(const lsdm_plan* plan, int prec, double alpha, const double* dA, const double* dB,
+                  double beta, double* dC, void* stream);
+
+/* Adjoint of the truncated product: for C = P_C(op(A) op(B)) and an upstream
+ * gradient dCbar on C's pattern,
+ *   dAbar += P_A(Cbar op(B)^T)   (P_A(op(B) Cbar^T) when A enters transposed)
+ *   dBbar += P_B(op(A)^T Cbar)   (P_B(Cbar^T op(A)) when B enters transposed)
+ * Either output may be NULL (not computed).  Both accumulate.  FP64 and FP32
+ * modes.  Errors: LSDM_EINVAL, LSDM_EUNSUPPORTED (other modes), LSDM_EDEVICE. */
+int lsdm_multiply_adjoint(const lsdm_plan* plan, int prec, const double* dCbar, const double* dA,
+                          const double* dB, double* dAbar, double* dBbar, void* stream);
+
+/* *dOut = sum over the blocks of p of <A_b, B_b>_F (= Tr(A B^T) over the
+ * pattern; Tr(AB) for symmetric B).  FP64 with per-thread compensated sums and
+ * a fixed-order tree, so the result is bitwise reproducible.  dOut: device. */
+int lsdm_dot(const lsdm_pattern* p, const double* dA, const double* dB, double* dOut, void* stream);
+
+/* ---- the LNV chain ------------------------------------------------------- */
+/* Patterns of S (range rS), H (rH) and L (rL) plus the intermediates
+ * X = LS (rL + rS), M = LSL (min(2 rL + rS, rH + rL + rS)) and every plan of
+ * the forward and adjoint chains.  These ranges drop only elements that cannot
+ * reach K on H's range or dE/dL on L's range, so E and dE/dL equal the
+ * untruncated algebra restricted to the S, H and L patterns.
+ * Errors: LSDM_EINVAL (a range < 0), LSDM_ENOMEM, LSDM_EDEVICE. */
+int lsdm_lnv_create(const lsdm_system* sys, double rS, double rH, double rL, lsdm_lnv** out);
+/* Borrowed views of the chain's patterns (owned by the lnv handle):
+ * which = 0 S, 1 H, 2 L, 3 X, 4 M. */
+int lsdm_lnv_pattern(const lsdm_lnv* lnv, int which, const lsdm_pattern** out);
+/* Work of one energy (grad = 0) or energy+gradient (grad = 1) evaluation:
+ * useful block triples and flops summed over the chain's products. */
+int lsdm_lnv_info(const lsdm_lnv* lnv, int grad, int64_t* n_triples, double* flops);
+/* K = 3 LSL - 2 LSLSL on H's pattern (eq. 3) and E = 2 <K, H> (FP64).
+ * dL, dS, dH: device doubles in block layout on the L, S, H patterns (symmetric
+ * matrices: block (j,i,-n) is the transpose of block (i,j,n)).
+ * dK: device, H's pattern, may be NULL.  dE: device, one double. */
+int lsdm_lnv_energy(lsdm_lnv* lnv, int prec, const double* dL, const double* dS, const double* dH,
+                    double* dK, double* dE, void* stream);
+/* E as above and dGradL = dE/dL on L's pattern, the derivative of eq. 3 with
+ * respect to each stored entry of L (blocks (i,j,n) and (j,i,-n) independent):
+ *   6 (HLS + SLH) - 4 (HLSLS + SLHLS + SLSLH)
+ * computed by the adjoint chain of the truncated products.  Modes FP64, FP32,
+ * BF16 (the adjoint products then run in the same mode).  dGradL: device. */
+int lsdm_lnv_energy_grad(lsdm_lnv* lnv, int prec, const double* dL, const double* dS, const double* dH,
+                         double* dE, double* dGradL, void* stream);
+/* Kernel timing of the chain's products: with enable = 1 every product launch
+ * of lsdm_lnv_energy(_grad) is bracketed by HIP events recorded on the call's
+ * stream (no extra synchronisation); enable = 0 stops and discards. */
+int lsdm_lnv_profile(lsdm_lnv* lnv, int enable);
+/* Waits for the recorded events, then returns per product (F1 F2 F3 B1 B2 B3
+ * B4 B5; host arrays of 8) the summed kernel milliseconds, the number of
+ * launches and the useful flops of one launch; clears the record. */
+int lsdm_lnv_profile_read(lsdm_lnv* lnv, double* ms, int64_t* launches, double* flops);
+void lsdm_lnv_destroy(lsdm_lnv* lnv);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char* lsdm_last_error(void);
+/* Library version string. */
+const char* lsdm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LSDM_H */

@@ -1,0 +1,531 @@
+// C ABI of the lsdm library (declared in include/lsdm.h).
+//
+// The LNV chain (Bowler & Miyazaki, eq. 3 and the energy 2 Tr(KH)):
+//   forward   F1  X = P_X(L S)        X on R_L + R_S
+//             F2  M = P_M(X L)        M on min(2 R_L + R_S, R_H + R_L + R_S)
+//             F3  P = P_H(X M)        (= LSLSL on H's range)
+//             K = 3 M|_H - 2 P,  E = 2 <K, H>
+//   adjoint   Kbar = 2H, Pbar = -4H
+//             B1  Mbar = 6H + P_M(X^T Pbar)
+//             B2  Xbar = P_X(Pbar M)
+//             B3  Xbar += P_X(Mbar L)
+//             B4  Lbar = P_L(X^T Mbar)
+//             B5  Lbar += P_L(Xbar S)
+// Taking LSLSL as X M = (LS)(LSL) keeps the chain equal to eq. 3 for any L, so
+// the adjoint yields dE/dL of eq. 3 itself: 6 (HLS + SLH) - 4 (HLSLS + SLHLS + SLSLH).
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "kernels.h"
+#include "lsdm_internal.h"
+
+namespace lsdm {
+void build_system(lsdm_system* s);
+void build_pattern_blocks(lsdm_pattern* p);
+void build_strips(lsdm_pattern* p);
+void build_plan(lsdm_plan* pl);
+
+static thread_local std::string g_last_error;
+void set_error(int code, const std::string& msg) {
+  (void)code;
+  g_last_error = msg;
+}
+
+// Without a HIP device the symbolic pass still runs on the host (patterns,
+// plans and their counts can be built and inspected) but device buffers stay
+// empty and every compute call fails with LSDM_EDEVICE.
+bool have_device() {
+  static int state = -1;
+  if (state < 0) {
+    int n = 0;
+    state = (hipGetDeviceCount(&n) == hipSuccess && n > 0) ? 1 : 0;
+    (void)hipGetLastError();
+  }
+  return state == 1;
+}
+static void require_device() {
+  if (!have_device()) LSDM_THROW(LSDM_EDEVICE, "no HIP device: compute calls need an MI355X (gfx950)");
+}
+
+DevBuf::~DevBuf() {
+  if (p) (void)hipFree(p);
+}
+void DevBuf::alloc(size_t nbytes) {
+  if (p) {
+    HIP_CHECK(hipFree(p));
+    p = nullptr;
+  }
+  bytes = 0;
+  if (nbytes == 0) nbytes = 16;
+  if (!have_device()) return;
+  HIP_CHECK(hipMalloc(&p, nbytes));
+  bytes = nbytes;
+}
+void DevBuf::upload(const void* host, size_t nbytes) {
+  alloc(nbytes);
+  if (nbytes && p) HIP_CHECK(hipMemcpy(p, host, nbytes, hipMemcpyHostToDevice));
+}
+
+template <class F>
+static int guarded(F&& f) {
+  try {
+    f();
+    g_last_error.clear();
+    return LSDM_OK;
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return LSDM_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return LSDM_EDEVICE;
+  }
+}
+
+static void check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) LSDM_THROW(LSDM_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+}
+
+static lsdm_pattern* make_pattern(const lsdm_system* sys, double R) {
+  if (!(R >= 0.0) || !std::isfinite(R)) LSDM_THROW(LSDM_EINVAL, "range must be finite and >= 0");
+  std::unique_ptr<lsdm_pattern> p(new lsdm_pattern());
+  p->sys = sys;
+  p->R = R;
+  build_pattern_blocks(p.get());
+  build_strips(p.get());
+  return p.release();
+}
+
+static lsdm_plan* make_plan(const lsdm_pattern* A, int tA, const lsdm_pattern* B, int tB, const lsdm_pattern* C) {
+  if (!A || !B || !C) LSDM_THROW(LSDM_EINVAL, "null pattern");
+  if (A->sys != B->sys || A->sys != C->sys) LSDM_THROW(LSDM_EPATTERN, "patterns belong to different systems");
+  std::unique_ptr<lsdm_plan> pl(new lsdm_plan());
+  pl->A = A;
+  pl->B = B;
+  pl->C = C;
+  pl->transA = tA ? 1 : 0;
+  pl->transB = tB ? 1 : 0;
+  build_plan(pl.get());
+  return pl.release();
+}
+
+static size_t strip_bytes(const lsdm_pattern* p, size_t elem) { return (size_t)p->n_strips * 64 * elem + 64; }
+
+// workspaces of a stand-alone multiply: strip copies of A, B (and B^T), C
+struct MulWork {
+  DevBuf a, b, bt, c;
+};
+
+template <class T>
+static void multiply_t(const lsdm_plan* pl, double alpha, const double* dA, const double* dB, double beta, double* dC,
+                       hipStream_t st) {
+  MulWork w;
+  w.a.alloc(strip_bytes(pl->A, sizeof(T)));
+  w.b.alloc(strip_bytes(pl->B, sizeof(T)));
+  w.c.alloc(strip_bytes(pl->C, sizeof(T)));
+  fill<T>(w.a.as<T>(), pl->A->n_strips * 64, (T)0, st);
+  fill<T>(w.b.as<T>(), pl->B->n_strips * 64, (T)0, st);
+  fill<T>(w.c.as<T>(), pl->C->n_strips * 64, (T)0, st);
+  user_to_strip<T>(pl->A, dA, w.a.as<T>(), 1.0, st);
+  user_to_strip<T>(pl->B, dB, w.b.as<T>(), 1.0, st);
+  const T* Bop = w.b.as<T>();
+  if (pl->transB) {
+    w.bt.alloc(strip_bytes(pl->B, sizeof(T)));
+    transpose_strips<T>(pl->B, w.b.as<T>(), w.bt.as<T>(), st);
+    Bop = w.bt.as<T>();
+  }
+  if (beta != 0.0) user_to_strip<T>(pl->C, dC, w.c.as<T>(), 1.0, st);
+  product<T>(pl, w.a.as<T>(), Bop, w.c.as<T>(), alpha, beta, st);
+  strip_to_user<T>(pl->C, w.c.as<T>(), dC, st);
+  check_launch();
+  HIP_CHECK(hipStreamSynchronize(st));   // the workspaces are released on return
+}
+
+// ---------------------------------------------------------------------------
+// the LNV chain
+// ---------------------------------------------------------------------------
+static void lnv_build(lsdm_lnv* L) {
+  const double rS = L->rS, rH = L->rH, rL = L->rL;
+  const double rX = rL + rS, rM = std::min(2 * rL + rS, rH + rL + rS);
+  L->pS = make_pattern(L->sys, rS);
+  L->pH = make_pattern(L->sys, rH);
+  L->pL = make_pattern(L->sys, rL);
+  L->pX = make_pattern(L->sys, rX);
+  L->pM = make_pattern(L->sys, rM);
+  L->F1 = make_plan(L->pL, 0, L->pS, 0, L->pX);
+  L->F2 = make_plan(L->pX, 0, L->pL, 0, L->pM);
+  L->F3 = make_plan(L->pX, 0, L->pM, 0, L->pH);
+  L->B1 = make_plan(L->pX, 1, L->pH, 0, L->pM);
+  L->B2 = make_plan(L->pH, 0, L->pM, 0, L->pX);
+  L->B3 = make_plan(L->pM, 0, L->pL, 0, L->pX);
+  L->B4 = make_plan(L->pX, 1, L->pM, 0, L->pL);
+  L->B5 = make_plan(L->pX, 0, L->pS, 0, L->pL);
+  // H strip -> M strip with the same (row, column quad, image); M's range
+  // contains H's, so every H strip has one
+  const lsdm_pattern* H = L->pH;
+  const lsdm_pattern* M = L->pM;
+  std::vector<i64> h2m(H->n_strips, -1);
+  for (i32 q = 0; q < L->sys->n_pseudo; ++q) {
+    i64 m = M->sptr[q];
+    for (i64 h = H->sptr[q]; h < H->sptr[q + 1]; ++h) {
+      const i64 key = skey(H->squad[h], H->simg[h]);
+      while (m < M->sptr[q + 1] && skey(M->squad[m], M->simg[m]) < key) ++m;
+      if (m >= M->sptr[q + 1] || skey(M->squad[m], M->simg[m]) != key)
+        LSDM_THROW(LSDM_EPATTERN, "H range exceeds the LSL range");
+      h2m[h] = m;
+    }
+  }
+  L->d_h2m.upload(h2m.data(), sizeof(i64) * h2m.size());
+  auto ws = [](DevBuf& b, const lsdm_pattern* p) { b.alloc(strip_bytes(p, sizeof(double))); };
+  ws(L->wL, L->pL);
+  ws(L->wS, L->pS);
+  ws(L->wH, L->pH);
+  ws(L->wH64, L->pH);
+  ws(L->wX, L->pX);
+  ws(L->wM, L->pM);
+  ws(L->wP, L->pH);
+  ws(L->wK, L->pH);
+  ws(L->wMb, L->pM);
+  ws(L->wXb, L->pX);
+  ws(L->wLb, L->pL);
+  L->wE.alloc(sizeof(double) * 2 * DOT_BLOCKS + 64);
+}
+
+// the chain's products in a fixed order: F1 F2 F3 B1 B2 B3 B4 B5
+static lsdm_plan* chain_plan(const lsdm_lnv* L, int w) {
+  lsdm_plan* p[8] = {L->F1, L->F2, L->F3, L->B1, L->B2, L->B3, L->B4, L->B5};
+  return p[w];
+}
+
+template <class T>
+static void chain_product(lsdm_lnv* L, int w, const T* A, const T* B, T* C, double alpha, double beta, hipStream_t st) {
+  if (!L->prof) {
+    product<T>(chain_plan(L, w), A, B, C, alpha, beta, st);
+    return;
+  }
+  while (L->ev_pool.size() < L->ev_used + 2) {
+    hipEvent_t e;
+    HIP_CHECK(hipEventCreate(&e));
+    L->ev_pool.push_back(e);
+  }
+  HIP_CHECK(hipEventRecord(L->ev_pool[L->ev_used], st));
+  product<T>(chain_plan(L, w), A, B, C, alpha, beta, st);
+  HIP_CHECK(hipEventRecord(L->ev_pool[L->ev_used + 1], st));
+  L->ev_used += 2;
+  L->ev_prod.push_back(w);
+}
+
+template <class T>
+static void lnv_forward(lsdm_lnv* L, const double* dL, const double* dS, const double* dH, double* dK, double* dE,
+                        hipStream_t st) {
+  T* wL = L->wL.as<T>();
+  T* wS = L->wS.as<T>();
+  T* wH = L->wH.as<T>();
+  T* wX = L->wX.as<T>();
+  T* wM = L->wM.as<T>();
+  T* wP = L->wP.as<T>();
+  double* wH64 = L->wH64.as<double>();
+  double* wK = L->wK.as<double>();
+  // inputs into strip layout (padding and out-of-range blocks stay zero)
+  fill<T>(wL, L->pL->n_strips * 64, (T)0, st);
+  fill<T>(wS, L->pS->n_strips * 64, (T)0, st);
+  fill<T>(wH, L->pH->n_strips * 64, (T)0, st);
+  fill<double>(wH64, L->pH->n_strips * 64, 0.0, st);
+  user_to_strip<T>(L->pL, dL, wL, 1.0, st);
+  user_to_strip<T>(L->pS, dS, wS, 1.0, st);
+  user_to_strip<T>(L->pH, dH, wH, 1.0, st);
+  user_to_strip<double>(L->pH, dH, wH64, 1.0, st);
+  chain_product<T>(L, 0, wL, wS, wX, 1.0, 0.0, st);     // X = LS
+  chain_product<T>(L, 1, wX, wL, wM, 1.0, 0.0, st);     // M = XL
+  chain_product<T>(L, 2, wX, wM, wP, 1.0, 0.0, st);     // P = XM on H's range
+  kassembly<T>(L, wM, wP, wK, st);                  // K = 3 M|_H - 2 P
+  dot(wK, wH64, L->pH->n_strips * 64, 2.0, L->wE.as<double>(), dE, st);   // E = 2 <K, H>
+  if (dK) strip_to_user<double>(L->pH, wK, dK, st);
+  check_launch();
+}
+
+template <class T>
+static void lnv_backward(lsdm_lnv* L, double* dG, hipStream_t st) {
+  T* wL = L->wL.as<T>();
+  T* wS = L->wS.as<T>();
+  T* wH = L->wH.as<T>();
+  T* wX = L->wX.as<T>();
+  T* wM = L->wM.as<T>();
+  T* wMb = L->wMb.as<T>();
+  T* wXb = L->wXb.as<T>();
+  T* wLb = L->wLb.as<T>();
+  fill<T>(wMb, L->pM->n_strips * 64, (T)0, st);
+  scatter_h<T>(L, wH, wMb, 6.0, st);                // Mbar = 3 Kbar = 6H on H's range
+  chain_product<T>(L, 3, wX, wH, wMb, -4.0, 1.0, st);    // Mbar += X^T Pbar,  Pbar = -4H
+  chain_product<T>(L, 4, wH, wM, wXb, -4.0, 0.0, st);    // Xbar  = Pbar M
+  chain_product<T>(L, 5, wMb, wL, wXb, 1.0, 1.0, st);    // Xbar += Mbar L
+  chain_product<T>(L, 6, wX, wMb, wLb, 1.0, 0.0, st);    // Lbar  = X^T Mbar
+  chain_product<T>(L, 7, wXb, wS, wLb, 1.0, 1.0, st);    // Lbar += Xbar S
+  strip_to_user<T>(L->pL, wLb, dG, st);
+  check_launch();
+}
+
+}  // namespace lsdm
+
+lsdm_lnv::~lsdm_lnv() {
+  for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+}
+
+using namespace lsdm;
+
+extern "C" {
+
+const char* lsdm_last_error(void) { return g_last_error.c_str(); }
+const char* lsdm_version(void) { return "lsdm 0.1 gfx950"; }
+
+int lsdm_system_create(int32_t n_atoms, const double* xyz, const int32_t* nfn, const double* lattice,
+                       lsdm_system** out) {
+  return guarded([&] {
+    if (!out || !xyz || !nfn || n_atoms <= 0) LSDM_THROW(LSDM_EINVAL, "null argument or n_atoms <= 0");
+    *out = nullptr;
+    std::unique_ptr<lsdm_system> s(new lsdm_system());
+    if (have_device()) HIP_CHECK(hipGetDevice(&s->device));
+    s->n_atoms = n_atoms;
+    s->xyz.assign(xyz, xyz + 3 * (size_t)n_atoms);
+    s->nfn.assign(nfn, nfn + n_atoms);
+    for (double v : s->xyz)
+      if (!std::isfinite(v)) LSDM_THROW(LSDM_EINVAL, "non-finite position");
+    for (i32 v : s->nfn)
+      if (v < 1 || v > 16) LSDM_THROW(LSDM_EINVAL, "nfn must lie in 1..16");
+    if (lattice) {
+      s->periodic = true;
+      for (int k = 0; k < 9; ++k) {
+        if (!std::isfinite(lattice[k])) LSDM_THROW(LSDM_EINVAL, "non-finite lattice");
+        s->lat[k] = lattice[k];
+      }
+    }
+    build_system(s.get());
+    *out = s.release();
+  });
+}
+
+void lsdm_system_destroy(lsdm_system* s) { delete s; }
+
+int lsdm_pattern_create(const lsdm_system* sys, double range, lsdm_pattern** out) {
+  return guarded([&] {
+    if (!sys || !out) LSDM_THROW(LSDM_EINVAL, "null argument");
+    *out = nullptr;
+    *out = make_pattern(sys, range);
+  });
+}
+
+int lsdm_pattern_info(const lsdm_pattern* p, int64_t* n_blocks, int64_t* n_values) {
+  return guarded([&] {
+    if (!p) LSDM_THROW(LSDM_EINVAL, "null pattern");
+    if (n_blocks) *n_blocks = (int64_t)p->col.size();
+    if (n_values) *n_values = p->nval;
+  });
+}
+
+int lsdm_pattern_export(const lsdm_pattern* p, int64_t* row_ptr, int32_t* col, int32_t* img3, int64_t* val_off) {
+  return guarded([&] {
+    if (!p) LSDM_THROW(LSDM_EINVAL, "null pattern");
+    if (row_ptr) std::memcpy(row_ptr, p->row_ptr.data(), sizeof(int64_t) * p->row_ptr.size());
+    if (col) std::memcpy(col, p->col.data(), sizeof(int32_t) * p->col.size());
+    if (val_off) std::memcpy(val_off, p->val_off.data(), sizeof(int64_t) * p->val_off.size());
+    if (img3)
+      for (size_t b = 0; b < p->img.size(); ++b) {
+        img3[3 * b] = img_c0(p->img[b]);
+        img3[3 * b + 1] = img_c1(p->img[b]);
+        img3[3 * b + 2] = img_c2(p->img[b]);
+      }
+  });
+}
+
+void lsdm_pattern_destroy(lsdm_pattern* p) { delete p; }
+
+int lsdm_plan_create(const lsdm_pattern* A, int transA, const lsdm_pattern* B, int transB, const lsdm_pattern* C,
+                     lsdm_plan** out) {
+  return guarded([&] {
+    if (!out) LSDM_THROW(LSDM_EINVAL, "null argument");
+    *out = nullptr;
+    *out = make_plan(A, transA, B, transB, C);
+  });
+}
+
+int lsdm_plan_info(const lsdm_plan* pl, int64_t* n_triples, double* flops, int64_t* plan_bytes) {
+  return guarded([&] {
+    if (!pl) LSDM_THROW(LSDM_EINVAL, "null plan");
+    if (n_triples) *n_triples = pl->n_triples;
+    if (flops) *flops = pl->flops;
+    if (plan_bytes) *plan_bytes = (int64_t)(pl->d_tiles.bytes + pl->d_steps.bytes);
+  });
+}
+
+void lsdm_plan_destroy(lsdm_plan* pl) { delete pl; }
+
+int lsdm_multiply(const lsdm_plan* pl, int prec, double alpha, const double* dA, const double* dB, double beta,
+                  double* dC, void* stream) {
+  return guarded([&] {
+    require_device();
+    if (!pl || !dA || !dB || !dC) LSDM_THROW(LSDM_EINVAL, "null argument");
+    if (dC == dA || dC == dB) LSDM_THROW(LSDM_EINVAL, "C must not alias A or B");
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == LSDM_FP64) multiply_t<double>(pl, alpha, dA, dB, beta, dC, st);
+    else if (prec == LSDM_FP32) multiply_t<float>(pl, alpha, dA, dB, beta, dC, st);
+    else LSDM_THROW(LSDM_EUNSUPPORTED, "precision mode not available for lsdm_multiply");
+  });
+}
+
+int lsdm_multiply_adjoint(const lsdm_plan* pl, int prec, const double* dCbar, const double* dA, const double* dB,
+                          double* dAbar, double* dBbar, void* stream) {
+  return guarded([&] {
+    require_device();
+    if (!pl || !dCbar || !dA || !dB) LSDM_THROW(LSDM_EINVAL, "null argument");
+    if (prec != LSDM_FP64 && prec != LSDM_FP32) LSDM_THROW(LSDM_EUNSUPPORTED, "adjoint supports FP64 and FP32");
+    hipStream_t st = (hipStream_t)stream;
+    auto run = [&](const lsdm_plan* q, const double* x, const double* y, double* out) {
+      if (prec == LSDM_FP64) multiply_t<double>(q, 1.0, x, y, 1.0, out, st);
+      else multiply_t<float>(q, 1.0, x, y, 1.0, out, st);
+    };
+    if (dAbar) {
+      // Abar += P_A(Cbar op(B)^T), or P_A(op(B) Cbar^T) when A enters transposed
+      std::unique_ptr<lsdm_plan> q(pl->transA ? make_plan(pl->B, pl->transB, pl->C, 1, pl->A)
+                                               : make_plan(pl->C, 0, pl->B, !pl->transB, pl->A));
+      if (pl->transA) run(q.get(), dB, dCbar, dAbar);
+      else run(q.get(), dCbar, dB, dAbar);
+    }
+    if (dBbar) {
+      // Bbar += P_B(op(A)^T Cbar), or P_B(Cbar^T op(A)) when B enters transposed
+      std::unique_ptr<lsdm_plan> q(pl->transB ? make_plan(pl->C, 1, pl->A, pl->transA, pl->B)
+                                               : make_plan(pl->A, !pl->transA, pl->C, 0, pl->B));
+      if (pl->transB) run(q.get(), dCbar, dA, dBbar);
+      else run(q.get(), dA, dCbar, dBbar);
+    }
+  });
+}
+
+int lsdm_dot(const lsdm_pattern* p, const double* dA, const double* dB, double* dOut, void* stream) {
+  return guarded([&] {
+    require_device();
+    if (!p || !dA || !dB || !dOut) LSDM_THROW(LSDM_EINVAL, "null argument");
+    DevBuf part;
+    part.alloc(sizeof(double) * 2 * DOT_BLOCKS);
+    hipStream_t st = (hipStream_t)stream;
+    dot(dA, dB, p->nval, 1.0, part.as<double>(), dOut, st);
+    check_launch();
+    HIP_CHECK(hipStreamSynchronize(st));
+  });
+}
+
+int lsdm_lnv_create(const lsdm_system* sys, double rS, double rH, double rL, lsdm_lnv** out) {
+  return guarded([&] {
+    if (!sys || !out) LSDM_THROW(LSDM_EINVAL, "null argument");
+    *out = nullptr;
+    for (double r : {rS, rH, rL})
+      if (!(r >= 0.0) || !std::isfinite(r)) LSDM_THROW(LSDM_EINVAL, "ranges must be finite and >= 0");
+    std::unique_ptr<lsdm_lnv> L(new lsdm_lnv());
+    L->sys = sys;
+    L->rS = rS;
+    L->rH = rH;
+    L->rL = rL;
+    try {
+      lnv_build(L.get());
+    } catch (...) {
+      lsdm_lnv_destroy(L.release());
+      throw;
+    }
+    *out = L.release();
+  });
+}
+
+int lsdm_lnv_pattern(const lsdm_lnv* L, int which, const lsdm_pattern** out) {
+  return guarded([&] {
+    if (!L || !out) LSDM_THROW(LSDM_EINVAL, "null argument");
+    const lsdm_pattern* ps[5] = {L->pS, L->pH, L->pL, L->pX, L->pM};
+    if (which < 0 || which > 4) LSDM_THROW(LSDM_EINVAL, "which must be 0..4");
+    *out = ps[which];
+  });
+}
+
+int lsdm_lnv_info(const lsdm_lnv* L, int grad, int64_t* n_triples, double* flops) {
+  return guarded([&] {
+    if (!L) LSDM_THROW(LSDM_EINVAL, "null argument");
+    const lsdm_plan* f[3] = {L->F1, L->F2, L->F3};
+    const lsdm_plan* b[5] = {L->B1, L->B2, L->B3, L->B4, L->B5};
+    int64_t nt = 0;
+    double fl = 0;
+    for (auto p : f) { nt += p->n_triples; fl += p->flops; }
+    if (grad)
+      for (auto p : b) { nt += p->n_triples; fl += p->flops; }
+    if (n_triples) *n_triples = nt;
+    if (flops) *flops = fl;
+  });
+}
+
+int lsdm_lnv_energy(lsdm_lnv* L, int prec, const double* dL, const double* dS, const double* dH, double* dK,
+                    double* dE, void* stream) {
+  return guarded([&] {
+    require_device();
+    if (!L || !dL || !dS || !dH || !dE) LSDM_THROW(LSDM_EINVAL, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == LSDM_FP64) lnv_forward<double>(L, dL, dS, dH, dK, dE, st);
+    else if (prec == LSDM_FP32) lnv_forward<float>(L, dL, dS, dH, dK, dE, st);
+    else LSDM_THROW(LSDM_EUNSUPPORTED, "precision mode not available");
+  });
+}
+
+int lsdm_lnv_energy_grad(lsdm_lnv* L, int prec, const double* dL, const double* dS, const double* dH, double* dE,
+                         double* dG, void* stream) {
+  return guarded([&] {
+    require_device();
+    if (!L || !dL || !dS || !dH || !dE || !dG) LSDM_THROW(LSDM_EINVAL, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == LSDM_FP64) {
+      lnv_forward<double>(L, dL, dS, dH, nullptr, dE, st);
+      lnv_backward<double>(L, dG, st);
+    } else if (prec == LSDM_FP32) {
+      lnv_forward<float>(L, dL, dS, dH, nullptr, dE, st);
+      lnv_backward<float>(L, dG, st);
+    } else {
+      LSDM_THROW(LSDM_EUNSUPPORTED, "precision mode not available");
+    }
+  });
+}
+
+int lsdm_lnv_profile(lsdm_lnv* L, int enable) {
+  return guarded([&] {
+    if (!L) LSDM_THROW(LSDM_EINVAL, "null argument");
+    L->prof = enable != 0;
+    L->ev_used = 0;
+    L->ev_prod.clear();
+  });
+}
+
+int lsdm_lnv_profile_read(lsdm_lnv* L, double* ms, int64_t* launches, double* flops) {
+  return guarded([&] {
+    if (!L || !ms || !launches || !flops) LSDM_THROW(LSDM_EINVAL, "null argument");
+    for (int w = 0; w < 8; ++w) {
+      ms[w] = 0.0;
+      launches[w] = 0;
+      flops[w] = chain_plan(L, w)->flops;
+    }
+    if (L->ev_used) HIP_CHECK(hipEventSynchronize(L->ev_pool[L->ev_used - 1]));
+    for (size_t k = 0; k < L->ev_prod.size(); ++k) {
+      float t = 0.f;
+      HIP_CHECK(hipEventElapsedTime(&t, L->ev_pool[2 * k], L->ev_pool[2 * k + 1]));
+      ms[L->ev_prod[k]] += t;
+      launches[L->ev_prod[k]] += 1;
+    }
+    L->ev_used = 0;
+    L->ev_prod.clear();
+  });
+}
+
+void lsdm_lnv_destroy(lsdm_lnv* L) {
+  if (!L) return;
+  for (lsdm_plan* p : {L->F1, L->F2, L->F3, L->B1, L->B2, L->B3, L->B4, L->B5}) delete p;
+  for (lsdm_pattern* p : {L->pS, L->pH, L->pL, L->pX, L->pM}) delete p;
+  delete L;
+}
+
+}  // extern "C"

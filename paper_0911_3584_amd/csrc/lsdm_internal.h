@@ -1,0 +1,175 @@
+// Internal data structures of the lsdm library (not part of the ABI).
+//
+// Internal layout ("strip layout").  Every atom is split into pseudo-atoms of
+// at most 4 support functions (an atom with nfn = 13 becomes 4 pseudo-atoms,
+// the last padded with 3 zero rows/columns), so all internal blocks are 4x4
+// and match the 4x4x4 multi-block MFMA forms of gfx950.  Atoms are ordered
+// along a Morton curve so that consecutive pseudo-atoms are spatially close;
+// a "quad" is 4 consecutive pseudo-atoms.  A matrix row (one pseudo-atom) is
+// stored as a list of strips, one per column quad (and lattice image) that
+// holds at least one in-range pair: 4 blocks of 4x4 = 64 values, block t for
+// pseudo-atom 4Q+t, zero where the pair is outside the range.  A 4-bit mask per
+// strip records which of its blocks lie in the pattern.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/lsdm.h"
+
+namespace lsdm {
+
+typedef int64_t i64;
+typedef int32_t i32;
+
+// -------- errors -----------------------------------------------------------
+struct Error {
+  int code;
+  std::string msg;
+};
+void set_error(int code, const std::string& msg);
+#define LSDM_THROW(code, msg) throw ::lsdm::Error{(code), (msg)}
+#define HIP_CHECK(x)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (x);                                                                 \
+    if (e_ != hipSuccess)                                                                \
+      LSDM_THROW(e_ == hipErrorOutOfMemory ? LSDM_ENOMEM : LSDM_EDEVICE,                 \
+                 std::string(#x) + ": " + hipGetErrorString(e_));                        \
+  } while (0)
+
+// -------- device buffers ---------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf();
+  void alloc(size_t nbytes);
+  void upload(const void* host, size_t nbytes);
+  template <class T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+// image (n0, n1, n2), each in [-128, 127], packed as offset binary so that the
+// packed integer orders lexicographically like the triple
+inline i32 img_pack(int n0, int n1, int n2) { return ((n0 + 128) << 16) | ((n1 + 128) << 8) | (n2 + 128); }
+__host__ __device__ inline int img_c0(i32 p) { return ((p >> 16) & 255) - 128; }
+__host__ __device__ inline int img_c1(i32 p) { return ((p >> 8) & 255) - 128; }
+__host__ __device__ inline int img_c2(i32 p) { return (p & 255) - 128; }
+__host__ __device__ inline i32 img_add(i32 a, i32 b) {  // a + b on unpacked triples
+  return (((img_c0(a) + img_c0(b)) + 128) << 16) | (((img_c1(a) + img_c1(b)) + 128) << 8) | ((img_c2(a) + img_c2(b)) + 128);
+}
+__host__ __device__ inline i32 img_neg(i32 a) {
+  return ((-img_c0(a) + 128) << 16) | ((-img_c1(a) + 128) << 8) | (-img_c2(a) + 128);
+}
+constexpr i32 IMG0 = (128 << 16) | (128 << 8) | 128;
+// strip key: column quad and image in one sortable 64-bit value
+__host__ __device__ inline i64 skey(i32 quad, i32 img) { return ((i64)quad << 24) | (i64)img; }
+
+}  // namespace lsdm
+
+// -------- handles ------------------------------------------------------------
+struct lsdm_system {
+  int device = 0;
+  lsdm::i32 n_atoms = 0;
+  std::vector<double> xyz;          // user order, 3 per atom
+  std::vector<lsdm::i32> nfn;       // user order
+  bool periodic = false;
+  double lat[9] = {0}, inv[9] = {0};
+  // Morton ordering and pseudo-atoms
+  std::vector<lsdm::i32> order;     // internal atom position -> user atom
+  std::vector<lsdm::i32> pbase;     // user atom -> first pseudo-atom
+  std::vector<lsdm::i32> npseudo;   // user atom -> number of pseudo-atoms
+  std::vector<lsdm::i32> patom;     // pseudo-atom -> user atom
+  std::vector<lsdm::i32> prows;     // pseudo-atom -> real rows (1..4)
+  lsdm::i32 n_pseudo = 0;           // padded to a multiple of 4
+  lsdm::i32 n_quads = 0;
+  lsdm::DevBuf d_prows;             // i32[n_pseudo]
+};
+
+struct lsdm_pattern {
+  const lsdm_system* sys = nullptr;
+  double R = 0;
+  // block layout (user), host
+  std::vector<lsdm::i64> row_ptr;   // n_atoms + 1
+  std::vector<lsdm::i32> col;       // user atom j
+  std::vector<lsdm::i32> img;       // packed image
+  std::vector<lsdm::i64> val_off;
+  lsdm::i64 nval = 0;
+  // strip layout, host
+  std::vector<lsdm::i64> sptr;      // n_pseudo + 1
+  std::vector<lsdm::i32> squad;     // column quad
+  std::vector<lsdm::i32> simg;      // packed image
+  std::vector<uint8_t> smask;       // 4-bit block mask
+  lsdm::i64 n_strips = 0;
+  // device copies
+  lsdm::DevBuf d_sptr, d_squad, d_simg, d_smask;
+  // block layout <-> strip layout map: one entry per 4x4 sub-block of every
+  // user block: user value offset of the sub-block's (0,0) element, its
+  // strip-layout offset, and its real extent (rows, cols, user row stride)
+  lsdm::i64 n_sub = 0;
+  lsdm::DevBuf d_sub_user, d_sub_strip, d_sub_shape;   // i64, i64, i32 (rows | cols<<8 | stride<<16)
+  // strip-layout index of every on-site (i, i, 0) sub-block, for the
+  // block-diagonal terms of the residual mode
+  lsdm::DevBuf d_diag_strip;        // i64 per pseudo-atom: offset of block (p, p, 0), -1 if none
+  // mirror map for transposes in strip layout: for strip s of row p, the
+  // strip index of (q, quad(p), -n) for each of its 4 blocks q
+  lsdm::DevBuf d_mirror;            // i64[4 * n_strips], -1 when absent
+};
+
+namespace lsdm {
+
+// One output tile of a product: a quad of 4 output rows x up to 4 column quads.
+struct Tile {
+  i32 row_quad;
+  i32 nsteps;
+  i64 step0;
+  i32 cstrip[16];   // output strip of slot (i, jq) = [4*i + jq], -1 if absent
+};
+
+// One step of a tile: a k pseudo-atom (with image) and its operands.
+//   a[i]: strip-layout offset / 16 of the 4x4 block A_{i,k} (or of X_{k,i} for a
+//         transposed A), -1 if absent
+//   b[jq]: strip index of B's strip (k, quad jq), -1 if absent
+//   mask: bit 4*i + jq set when slot (i, jq) has at least one useful triple
+struct Step {
+  i32 a[4];
+  i32 b[4];
+  uint32_t mask;
+};
+
+}  // namespace lsdm
+
+struct lsdm_plan {
+  const lsdm_pattern* A = nullptr;
+  const lsdm_pattern* B = nullptr;
+  const lsdm_pattern* C = nullptr;
+  int transA = 0, transB = 0;
+  lsdm::i64 n_tiles = 0, n_steps = 0, n_triples = 0;
+  double flops = 0;
+  lsdm::DevBuf d_tiles, d_steps;
+  // for a transposed B the plan multiplies by a materialised transpose
+  lsdm::DevBuf d_bT;                // strip-layout workspace of B^T (doubles)
+};
+
+struct lsdm_lnv {
+  const lsdm_system* sys = nullptr;
+  double rS = 0, rH = 0, rL = 0;
+  lsdm_pattern *pS = nullptr, *pH = nullptr, *pL = nullptr, *pX = nullptr, *pM = nullptr;
+  lsdm_plan *F1 = nullptr, *F2 = nullptr, *F3 = nullptr;
+  lsdm_plan *B1 = nullptr, *B2 = nullptr, *B3 = nullptr, *B4 = nullptr, *B5 = nullptr;
+  lsdm::i64 max_strips = 0;
+  // strip-layout workspaces (sized for FP64)
+  lsdm::DevBuf wL, wS, wH, wH64, wX, wM, wP, wMb, wXb, wLb, wK;
+  lsdm::DevBuf wE;                  // partial sums for the energy
+  // map from H's strips to M's strips (K assembly and 6H into Mbar)
+  lsdm::DevBuf d_h2m;               // i64 per H strip: M strip index
+  // optional kernel timing: event pairs around product launches
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<int> ev_prod;         // product index 0..7 of each recorded pair
+  ~lsdm_lnv();
+};

@@ -1,0 +1,513 @@
+// Symbolic pass, host side: system ordering, range patterns (cell-list
+// neighbour search), the strip layout of a pattern and the tile/step task
+// lists of truncated products.
+//
+// Source of the operations: Bowler & Miyazaki, section 2.  A range pattern is
+// the set of atom pairs within the cutoff (stated after eq. 3); a truncated
+// product keeps only the output blocks of its own range pattern.  The
+// partition/bundle ordering of the paper's parallel scheme (Hilbert curves) is
+// replaced here by a Morton ordering of atoms, used only so that consecutive
+// pseudo-atoms are close in space and 4x4 block groups of the MFMA kernels
+// share neighbours.
+#include <algorithm>
+#include <array>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <thread>
+#include <unordered_map>
+
+#include "lsdm_internal.h"
+
+namespace lsdm {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+template <class F>
+void parallel_for(i64 n, F&& f, int grain = 16) {
+  unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+  if (n < 2 * grain || nt == 1) {
+    for (i64 i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::atomic<i64> next(0);
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < nt; ++t)
+    th.emplace_back([&]() {
+      for (;;) {
+        i64 s = next.fetch_add(grain);
+        if (s >= n) break;
+        i64 e = std::min(n, s + (i64)grain);
+        for (i64 i = s; i < e; ++i) f(i);
+      }
+    });
+  for (auto& t : th) t.join();
+}
+
+static void invert3(const double* T, double* inv) {
+  double a = T[0], b = T[1], c = T[2], d = T[3], e = T[4], f = T[5], g = T[6], h = T[7], k = T[8];
+  double det = a * (e * k - f * h) - b * (d * k - f * g) + c * (d * h - e * g);
+  if (!(std::fabs(det) > 0) || !std::isfinite(det)) LSDM_THROW(LSDM_EINVAL, "lattice is singular");
+  inv[0] = (e * k - f * h) / det; inv[1] = (c * h - b * k) / det; inv[2] = (b * f - c * e) / det;
+  inv[3] = (f * g - d * k) / det; inv[4] = (a * k - c * g) / det; inv[5] = (c * d - a * f) / det;
+  inv[6] = (d * h - e * g) / det; inv[7] = (b * g - a * h) / det; inv[8] = (a * e - b * d) / det;
+}
+
+static uint64_t spread3(uint64_t v) {  // 21 bits -> every third bit
+  v &= 0x1fffff;
+  v = (v | v << 32) & 0x1f00000000ffffULL;
+  v = (v | v << 16) & 0x1f0000ff0000ffULL;
+  v = (v | v << 8) & 0x100f00f00f00f00fULL;
+  v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+  v = (v | v << 2) & 0x1249249249249249ULL;
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// system: Morton order and pseudo-atoms
+// ---------------------------------------------------------------------------
+void build_system(lsdm_system* s) {
+  const i32 n = s->n_atoms;
+  std::vector<double> f(3 * (size_t)n);
+  if (s->periodic) {
+    invert3(s->lat, s->inv);
+    for (i32 a = 0; a < n; ++a)
+      for (int k = 0; k < 3; ++k) {
+        double v = s->xyz[3 * a] * s->inv[k] + s->xyz[3 * a + 1] * s->inv[3 + k] + s->xyz[3 * a + 2] * s->inv[6 + k];
+        f[3 * a + k] = v - std::floor(v);
+      }
+  } else {
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (i32 a = 0; a < n; ++a)
+      for (int k = 0; k < 3; ++k) {
+        lo[k] = std::min(lo[k], s->xyz[3 * a + k]);
+        hi[k] = std::max(hi[k], s->xyz[3 * a + k]);
+      }
+    double span = 1e-30;
+    for (int k = 0; k < 3; ++k) span = std::max(span, hi[k] - lo[k]);
+    for (i32 a = 0; a < n; ++a)
+      for (int k = 0; k < 3; ++k) f[3 * a + k] = (s->xyz[3 * a + k] - lo[k]) / span;
+  }
+  std::vector<uint64_t> code(n);
+  const double scale = (double)((1 << 21) - 1);
+  for (i32 a = 0; a < n; ++a) {
+    uint64_t q[3];
+    for (int k = 0; k < 3; ++k) q[k] = (uint64_t)std::min(scale, std::max(0.0, std::floor(f[3 * a + k] * scale)));
+    code[a] = spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2);
+  }
+  s->order.resize(n);
+  std::iota(s->order.begin(), s->order.end(), 0);
+  std::stable_sort(s->order.begin(), s->order.end(), [&](i32 x, i32 y) { return code[x] < code[y]; });
+  s->pbase.assign(n, 0);
+  s->npseudo.assign(n, 0);
+  s->patom.clear();
+  s->prows.clear();
+  for (i32 pos = 0; pos < n; ++pos) {
+    i32 a = s->order[pos];
+    i32 np = (s->nfn[a] + 3) / 4;
+    s->pbase[a] = (i32)s->patom.size();
+    s->npseudo[a] = np;
+    for (i32 t = 0; t < np; ++t) {
+      s->patom.push_back(a);
+      s->prows.push_back(std::min(4, s->nfn[a] - 4 * t));
+    }
+  }
+  while (s->patom.size() % 4) {  // padding pseudo-atoms: no rows, no blocks
+    s->patom.push_back(-1);
+    s->prows.push_back(0);
+  }
+  s->n_pseudo = (i32)s->patom.size();
+  s->n_quads = s->n_pseudo / 4;
+  s->d_prows.upload(s->prows.data(), sizeof(i32) * s->prows.size());
+}
+
+// ---------------------------------------------------------------------------
+// range pattern, block layout: cell-list neighbour search
+//   all (i, j, n) with |x_j + n T - x_i|^2 <= R^2, rows sorted by (j, n)
+// Atoms are binned on fractional coordinates with bins wider than R across
+// each pair of lattice planes, so every partner lies within D bins (D = 1
+// unless the cell is thinner than R, when the bin/image pairs wrap around).
+// The distance is evaluated from the caller's positions as
+//   (x_j - x_i) + (n0 T0 + n1 T1 + n2 T2), component by component.
+// ---------------------------------------------------------------------------
+void build_pattern_blocks(lsdm_pattern* p) {
+  const lsdm_system* s = p->sys;
+  const i32 n = s->n_atoms;
+  const double R = p->R, R2 = R * R;
+  int nb[3] = {1, 1, 1}, D[3] = {1, 1, 1};
+  std::vector<int> wrap(3 * (size_t)n, 0);
+  std::vector<int> bin(3 * (size_t)n, 0);
+  if (s->periodic) {
+    for (int k = 0; k < 3; ++k) {
+      const double bn = std::sqrt(s->inv[k] * s->inv[k] + s->inv[3 + k] * s->inv[3 + k] + s->inv[6 + k] * s->inv[6 + k]);
+      const double w = 1.0 / bn;   // distance between the lattice planes of axis k
+      const double width = std::max(R * (1.0 + 1e-9), 1e-300);
+      nb[k] = (int)std::max(1.0, std::min(1024.0, std::floor(w / width)));
+      D[k] = (int)std::floor(R * nb[k] / w) + 1;
+      if (2 * D[k] + 1 > 255) LSDM_THROW(LSDM_EUNSUPPORTED, "range too large for the image encoding");
+    }
+    for (i32 a = 0; a < n; ++a)
+      for (int k = 0; k < 3; ++k) {
+        double f = s->xyz[3 * a] * s->inv[k] + s->xyz[3 * a + 1] * s->inv[3 + k] + s->xyz[3 * a + 2] * s->inv[6 + k];
+        double fl = std::floor(f);
+        wrap[3 * a + k] = (int)fl;
+        int b = (int)std::floor((f - fl) * nb[k]);
+        bin[3 * a + k] = std::min(nb[k] - 1, std::max(0, b));
+      }
+  } else {
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (i32 a = 0; a < n; ++a)
+      for (int k = 0; k < 3; ++k) {
+        lo[k] = std::min(lo[k], s->xyz[3 * a + k]);
+        hi[k] = std::max(hi[k], s->xyz[3 * a + k]);
+      }
+    const double width = std::max(R * (1.0 + 1e-9), 1e-9);
+    for (int k = 0; k < 3; ++k) nb[k] = (int)std::max(1.0, std::min(1024.0, std::floor((hi[k] - lo[k]) / width) + 1));
+    for (i32 a = 0; a < n; ++a)
+      for (int k = 0; k < 3; ++k)
+        bin[3 * a + k] = std::min(nb[k] - 1, std::max(0, (int)std::floor((s->xyz[3 * a + k] - lo[k]) / width)));
+  }
+  const i64 ncell = (i64)nb[0] * nb[1] * nb[2];
+  std::vector<i64> cstart(ncell + 1, 0);
+  std::vector<i32> catom(n);
+  auto cid = [&](int b0, int b1, int b2) { return ((i64)b0 * nb[1] + b1) * nb[2] + b2; };
+  for (i32 a = 0; a < n; ++a) ++cstart[cid(bin[3 * a], bin[3 * a + 1], bin[3 * a + 2]) + 1];
+  for (i64 c = 0; c < ncell; ++c) cstart[c + 1] += cstart[c];
+  {
+    std::vector<i64> w(cstart.begin(), cstart.end() - 1);
+    for (i32 a = 0; a < n; ++a) catom[w[cid(bin[3 * a], bin[3 * a + 1], bin[3 * a + 2])]++] = a;
+  }
+  std::vector<std::vector<std::pair<i64, i32>>> rows(n);   // ((j << 24) | img) per row
+  std::atomic<int> bad(0);
+  parallel_for(n, [&](i64 i) {
+    auto& r = rows[i];
+    const double xi = s->xyz[3 * i], yi = s->xyz[3 * i + 1], zi = s->xyz[3 * i + 2];
+    for (int d0 = -D[0]; d0 <= D[0]; ++d0)
+      for (int d1 = -D[1]; d1 <= D[1]; ++d1)
+        for (int d2 = -D[2]; d2 <= D[2]; ++d2) {
+          int t[3] = {bin[3 * i] + d0, bin[3 * i + 1] + d1, bin[3 * i + 2] + d2}, sh[3] = {0, 0, 0};
+          bool skip = false;
+          for (int k = 0; k < 3; ++k) {
+            if (s->periodic) {
+              int q = (t[k] >= 0) ? t[k] / nb[k] : -((-t[k] + nb[k] - 1) / nb[k]);
+              sh[k] = q;
+              t[k] -= q * nb[k];
+            } else if (t[k] < 0 || t[k] >= nb[k]) {
+              skip = true;
+            }
+          }
+          if (skip) continue;
+          const i64 c = cid(t[0], t[1], t[2]);
+          for (i64 u = cstart[c]; u < cstart[c + 1]; ++u) {
+            const i32 j = catom[u];
+            int m0 = 0, m1 = 0, m2 = 0;
+            double dx = s->xyz[3 * j] - xi, dy = s->xyz[3 * j + 1] - yi, dz = s->xyz[3 * j + 2] - zi;
+            if (s->periodic) {
+              m0 = sh[0] - wrap[3 * j] + wrap[3 * i];
+              m1 = sh[1] - wrap[3 * j + 1] + wrap[3 * i + 1];
+              m2 = sh[2] - wrap[3 * j + 2] + wrap[3 * i + 2];
+              const double* T = s->lat;
+              dx = dx + ((double)m0 * T[0] + (double)m1 * T[3] + (double)m2 * T[6]);
+              dy = dy + ((double)m0 * T[1] + (double)m1 * T[4] + (double)m2 * T[7]);
+              dz = dz + ((double)m0 * T[2] + (double)m1 * T[5] + (double)m2 * T[8]);
+            }
+            if (dx * dx + dy * dy + dz * dz <= R2) {
+              if (m0 < -127 || m0 > 127 || m1 < -127 || m1 > 127 || m2 < -127 || m2 > 127) { bad = 1; continue; }
+              r.push_back({((i64)j << 24) | img_pack(m0, m1, m2), 0});
+            }
+          }
+        }
+    std::sort(r.begin(), r.end());
+  }, 8);
+  if (bad) LSDM_THROW(LSDM_EUNSUPPORTED, "lattice image index beyond +-127");
+  p->row_ptr.assign(n + 1, 0);
+  for (i32 a = 0; a < n; ++a) p->row_ptr[a + 1] = p->row_ptr[a] + (i64)rows[a].size();
+  const i64 nb_tot = p->row_ptr[n];
+  if (nb_tot >= (i64)1 << 31) LSDM_THROW(LSDM_ENOMEM, "pattern exceeds 2^31 blocks");
+  p->col.resize(nb_tot);
+  p->img.resize(nb_tot);
+  parallel_for(n, [&](i64 a) {
+    i64 w = p->row_ptr[a];
+    for (auto& e : rows[a]) {
+      p->col[w] = (i32)(e.first >> 24);
+      p->img[w] = (i32)(e.first & 0xffffff);
+      ++w;
+    }
+  });
+}
+
+// ---------------------------------------------------------------------------
+// strip layout of a pattern whose block layout (row_ptr, col, img) is filled
+// ---------------------------------------------------------------------------
+static i64 find_strip(const lsdm_pattern* p, i32 row, i64 key) {
+  i64 lo = p->sptr[row], hi = p->sptr[row + 1];
+  while (lo < hi) {
+    i64 mid = (lo + hi) >> 1;
+    i64 k = skey(p->squad[mid], p->simg[mid]);
+    if (k < key) lo = mid + 1; else hi = mid;
+  }
+  if (lo < p->sptr[row + 1] && skey(p->squad[lo], p->simg[lo]) == key) return lo;
+  return -1;
+}
+
+void build_strips(lsdm_pattern* p) {
+  const lsdm_system* s = p->sys;
+  const i32 n = s->n_atoms, np = s->n_pseudo;
+  // block layout value offsets
+  p->val_off.resize(p->col.size());
+  i64 off = 0;
+  for (i32 a = 0; a < n; ++a)
+    for (i64 b = p->row_ptr[a]; b < p->row_ptr[a + 1]; ++b) {
+      p->val_off[b] = off;
+      off += (i64)s->nfn[a] * s->nfn[p->col[b]];
+    }
+  p->nval = off;
+  // strips per pseudo-row: (quad, image) -> mask
+  std::vector<std::vector<std::pair<i64, uint8_t>>> rows(np);
+  parallel_for(n, [&](i64 a) {
+    for (i32 sa = 0; sa < s->npseudo[a]; ++sa) {
+      i32 pa = s->pbase[a] + sa;
+      auto& r = rows[pa];
+      for (i64 b = p->row_ptr[a]; b < p->row_ptr[a + 1]; ++b) {
+        i32 j = p->col[b];
+        for (i32 sb = 0; sb < s->npseudo[j]; ++sb) {
+          i32 pb = s->pbase[j] + sb;
+          r.push_back({skey(pb >> 2, p->img[b]), (uint8_t)(1u << (pb & 3))});
+        }
+      }
+      std::sort(r.begin(), r.end());
+      size_t w = 0;
+      for (size_t t = 0; t < r.size(); ++t) {
+        if (w > 0 && r[w - 1].first == r[t].first) r[w - 1].second |= r[t].second;
+        else r[w++] = r[t];
+      }
+      r.resize(w);
+    }
+  });
+  p->sptr.assign(np + 1, 0);
+  for (i32 q = 0; q < np; ++q) p->sptr[q + 1] = p->sptr[q] + (i64)rows[q].size();
+  p->n_strips = p->sptr[np];
+  if (p->n_strips >= (i64)1 << 29) LSDM_THROW(LSDM_ENOMEM, "pattern too large for 32-bit strip indices");
+  p->squad.resize(p->n_strips);
+  p->simg.resize(p->n_strips);
+  p->smask.resize(p->n_strips);
+  parallel_for(np, [&](i64 q) {
+    i64 w = p->sptr[q];
+    for (auto& e : rows[q]) {
+      p->squad[w] = (i32)(e.first >> 24);
+      p->simg[w] = (i32)(e.first & 0xffffff);
+      p->smask[w] = e.second;
+      ++w;
+    }
+  });
+  rows.clear();
+  rows.shrink_to_fit();
+  // sub-block maps between the two layouts
+  std::vector<i64> subcnt(n + 1, 0);
+  for (i32 a = 0; a < n; ++a) {
+    i64 c = 0;
+    for (i64 b = p->row_ptr[a]; b < p->row_ptr[a + 1]; ++b) c += (i64)s->npseudo[a] * s->npseudo[p->col[b]];
+    subcnt[a + 1] = subcnt[a] + c;
+  }
+  p->n_sub = subcnt[n];
+  std::vector<i64> su(p->n_sub), ss(p->n_sub);
+  std::vector<i32> sh(p->n_sub);
+  parallel_for(n, [&](i64 a) {
+    i64 w = subcnt[a];
+    for (i64 b = p->row_ptr[a]; b < p->row_ptr[a + 1]; ++b) {
+      i32 j = p->col[b];
+      for (i32 sa = 0; sa < s->npseudo[a]; ++sa)
+        for (i32 sb = 0; sb < s->npseudo[j]; ++sb) {
+          i32 pa = s->pbase[a] + sa, pb = s->pbase[j] + sb;
+          i64 st = find_strip(p, pa, skey(pb >> 2, p->img[b]));
+          if (st < 0) LSDM_THROW(LSDM_EDEVICE, "internal: strip of a pattern block not found");
+          su[w] = p->val_off[b] + (i64)(4 * sa) * s->nfn[j] + 4 * sb;
+          ss[w] = st * 64 + (pb & 3) * 16;
+          sh[w] = s->prows[pa] | (s->prows[pb] << 8) | (s->nfn[j] << 16);
+          ++w;
+        }
+    }
+  });
+  p->d_sub_user.upload(su.data(), sizeof(i64) * su.size());
+  p->d_sub_strip.upload(ss.data(), sizeof(i64) * ss.size());
+  p->d_sub_shape.upload(sh.data(), sizeof(i32) * sh.size());
+  // on-site sub-blocks: every (p, p, 0) pair
+  std::vector<i64> diag(np, -1);
+  for (i32 q = 0; q < np; ++q) {
+    if (s->patom[q] < 0) continue;
+    i64 st = find_strip(p, q, skey(q >> 2, IMG0));
+    if (st >= 0 && (p->smask[st] >> (q & 3) & 1)) diag[q] = st * 64 + (q & 3) * 16;
+  }
+  p->d_diag_strip.upload(diag.data(), sizeof(i64) * diag.size());
+  // mirror map: block t of strip s in row q is (q, 4Q+t, n); its mirror is
+  // (4Q+t, q, -n), found in strip (4Q+t, quad(q), -n) at block q & 3
+  std::vector<i64> mir(4 * (size_t)p->n_strips, -1);
+  parallel_for(np, [&](i64 q) {
+    for (i64 st = p->sptr[q]; st < p->sptr[q + 1]; ++st)
+      for (int t = 0; t < 4; ++t) {
+        if (!(p->smask[st] >> t & 1)) continue;
+        i32 r = 4 * p->squad[st] + t;
+        const i64 ms = find_strip(p, r, skey((i32)(q >> 2), img_neg(p->simg[st])));
+        mir[4 * st + t] = ms < 0 ? -1 : ms * 64 + (q & 3) * 16;
+      }
+  });
+  p->d_mirror.upload(mir.data(), sizeof(i64) * mir.size());
+  p->d_sptr.upload(p->sptr.data(), sizeof(i64) * p->sptr.size());
+  p->d_squad.upload(p->squad.data(), sizeof(i32) * p->squad.size());
+  p->d_simg.upload(p->simg.data(), sizeof(i32) * p->simg.size());
+  p->d_smask.upload(p->smask.data(), p->smask.size());
+}
+
+// ---------------------------------------------------------------------------
+// product plan: tiles (4 output rows x up to 4 output column quads) and steps
+// ---------------------------------------------------------------------------
+void build_plan(lsdm_plan* pl) {
+  const lsdm_pattern* A = pl->A;
+  const lsdm_pattern* B = pl->B;
+  const lsdm_pattern* C = pl->C;
+  const lsdm_system* s = C->sys;
+  const i32 nq = s->n_quads;
+  std::vector<std::vector<Tile>> tiles(nq);
+  std::vector<std::vector<Step>> steps(nq);
+  std::vector<i64> triples(nq, 0);
+  std::vector<double> flops(nq, 0.0);
+  const bool tA = pl->transA != 0;
+  parallel_for(nq, [&](i64 I) {
+    // k-list: the union over the 4 rows of A's blocks (k, m) with the pointer of
+    // each row's block; for a transposed A the row pattern is A's own (range
+    // patterns are symmetric) and the block is the transpose of A_{k,(i,-m)}
+    std::vector<std::pair<i64, std::array<i32, 4>>> kl;
+    {
+      std::vector<std::pair<i64, std::pair<int, i32>>> raw;
+      for (int ii = 0; ii < 4; ++ii) {
+        i32 row = 4 * (i32)I + ii;
+        for (i64 st = A->sptr[row]; st < A->sptr[row + 1]; ++st)
+          for (int t = 0; t < 4; ++t) {
+            if (!(A->smask[st] >> t & 1)) continue;
+            i32 k = 4 * A->squad[st] + t;
+            i32 m = A->simg[st];
+            i64 blk;
+            if (!tA) {
+              blk = st * 4 + t;
+            } else {
+              i64 ms = find_strip(A, k, skey(row >> 2, img_neg(m)));
+              if (ms < 0) LSDM_THROW(LSDM_EPATTERN, "transposed operand pattern is not symmetric");
+              blk = ms * 4 + (row & 3);
+            }
+            raw.push_back({((i64)k << 24) | m, {ii, (i32)blk}});
+          }
+      }
+      std::sort(raw.begin(), raw.end());
+      for (auto& e : raw) {
+        if (kl.empty() || kl.back().first != e.first) kl.push_back({e.first, {-1, -1, -1, -1}});
+        kl.back().second[e.second.first] = e.second.second;
+      }
+    }
+    // output column quads of the 4 rows of C, grouped 4 per tile
+    std::vector<i64> ckeys;
+    for (int ii = 0; ii < 4; ++ii) {
+      i32 row = 4 * (i32)I + ii;
+      for (i64 st = C->sptr[row]; st < C->sptr[row + 1]; ++st) ckeys.push_back(skey(C->squad[st], C->simg[st]));
+    }
+    std::sort(ckeys.begin(), ckeys.end());
+    ckeys.erase(std::unique(ckeys.begin(), ckeys.end()), ckeys.end());
+    const i64 nt = ((i64)ckeys.size() + 3) / 4;
+    std::vector<Tile> T(nt);
+    std::vector<uint8_t> cm(nt * 16, 0);
+    std::unordered_map<i64, i32> cpos;   // column key -> 4*tile + jq
+    cpos.reserve(ckeys.size() * 2);
+    for (size_t c = 0; c < ckeys.size(); ++c) cpos[ckeys[c]] = (i32)c;
+    for (i64 t = 0; t < nt; ++t) {
+      T[t].row_quad = (i32)I;
+      for (int q = 0; q < 16; ++q) T[t].cstrip[q] = -1;
+    }
+    for (int ii = 0; ii < 4; ++ii) {
+      i32 row = 4 * (i32)I + ii;
+      for (i64 st = C->sptr[row]; st < C->sptr[row + 1]; ++st) {
+        i32 c = cpos[skey(C->squad[st], C->simg[st])];
+        T[c / 4].cstrip[4 * ii + (c & 3)] = (i32)st;
+        cm[(c / 4) * 16 + 4 * ii + (c & 3)] = C->smask[st];
+      }
+    }
+    // per tile and k: the B strips reaching its column quads
+    const size_t nk = kl.size();
+    std::vector<i32> bidx(nt * nk * 4, -1);
+    std::vector<uint8_t> bmask(nt * nk * 4, 0);
+    for (size_t kk = 0; kk < nk; ++kk) {
+      i32 k = (i32)(kl[kk].first >> 24);
+      i32 m = (i32)(kl[kk].first & 0xffffff);
+      for (i64 st = B->sptr[k]; st < B->sptr[k + 1]; ++st) {
+        auto it = cpos.find(skey(B->squad[st], img_add(m, B->simg[st])));
+        if (it == cpos.end()) continue;   // outside C's range for every row: truncated
+        i32 c = it->second;
+        size_t w = ((size_t)(c / 4) * nk + kk) * 4 + (c & 3);
+        bidx[w] = (i32)st;
+        bmask[w] = B->smask[st];
+      }
+    }
+    auto& S = steps[I];
+    for (i64 t = 0; t < nt; ++t) {
+      T[t].step0 = (i64)S.size();
+      for (size_t kk = 0; kk < nk; ++kk) {
+        Step st;
+        st.mask = 0;
+        i32 k = (i32)(kl[kk].first >> 24);
+        for (int ii = 0; ii < 4; ++ii) st.a[ii] = kl[kk].second[ii];
+        for (int jq = 0; jq < 4; ++jq) st.b[jq] = bidx[((size_t)t * nk + kk) * 4 + jq];
+        for (int ii = 0; ii < 4; ++ii) {
+          if (st.a[ii] < 0) continue;
+          for (int jq = 0; jq < 4; ++jq) {
+            if (st.b[jq] < 0) continue;
+            uint8_t u = bmask[((size_t)t * nk + kk) * 4 + jq] & cm[t * 16 + 4 * ii + jq];
+            if (!u) continue;
+            st.mask |= 1u << (4 * ii + jq);
+            const i32 ri = s->prows[4 * I + ii], rk = s->prows[k];
+            const i32 jbase = 4 * (i32)(ckeys[4 * t + jq] >> 24);
+            for (int b = 0; b < 4; ++b) {
+              if (!(u >> b & 1)) continue;
+              flops[I] += 2.0 * ri * rk * s->prows[jbase + b];
+              // count each atom triple once: the first pseudo-atom of every atom
+              const i32 pi = 4 * (i32)I + ii, pj = jbase + b;
+              if (pi == s->pbase[s->patom[pi]] && k == s->pbase[s->patom[k]] && pj == s->pbase[s->patom[pj]])
+                ++triples[I];
+            }
+          }
+        }
+        if (st.mask) S.push_back(st);
+      }
+      T[t].nsteps = (i32)((i64)S.size() - T[t].step0);
+    }
+    tiles[I] = std::move(T);
+  }, 4);
+  // concatenate
+  i64 ntile = 0, nstep = 0;
+  for (i32 I = 0; I < nq; ++I) {
+    ntile += (i64)tiles[I].size();
+    nstep += (i64)steps[I].size();
+  }
+  std::vector<Tile> allT;
+  allT.reserve(ntile);
+  std::vector<Step> allS;
+  allS.reserve(nstep);
+  pl->n_triples = 0;
+  pl->flops = 0;
+  for (i32 I = 0; I < nq; ++I) {
+    i64 base = (i64)allS.size();
+    for (auto t : tiles[I]) {
+      t.step0 += base;
+      allT.push_back(t);
+    }
+    allS.insert(allS.end(), steps[I].begin(), steps[I].end());
+    pl->n_triples += triples[I];
+    pl->flops += flops[I];
+    std::vector<Step>().swap(steps[I]);
+  }
+  pl->n_tiles = ntile;
+  pl->n_steps = nstep;
+  pl->d_tiles.upload(allT.data(), sizeof(Tile) * allT.size());
+  pl->d_steps.upload(allS.data(), sizeof(Step) * allS.size());
+}
+
+}  // namespace lsdm

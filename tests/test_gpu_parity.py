@@ -1,0 +1,188 @@
+"""GPU parity: the HIP path against the FP64 oracle on the same seeded inputs.
+
+FP64 bar (stated target): relative error <= 1e-12 for E, and in Frobenius norm
+for every product, K and dE/dL.  FP32 products are held to the a-priori bound
+of the FP32 rounding of inputs and accumulation (see test_gpu_precision.py).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests._sides import gpu_values, rel, same_pattern
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_0911_3584_amd as lsdm  # noqa: E402
+
+DEV = "cuda:0"
+TOL64 = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def T(x):
+    return torch.from_numpy(np.ascontiguousarray(x, np.float64)).to(DEV)
+
+
+# ---------------------------------------------------------------------------
+# single truncated products
+# ---------------------------------------------------------------------------
+PRODUCT_CASES = [
+    # name, system factory, (rA, rB, rC), transA, transB, alpha, beta
+    ("si64_lossless", lambda: workloads.diamond(2), (12.0, 8.0, 20.0), 0, 0, 1.0, 0.0),
+    ("si64_lossy", lambda: workloads.diamond(2), (20.0, 12.0, 24.0), 0, 0, 1.0, 0.0),
+    ("si64_small_out", lambda: workloads.diamond(2), (24.0, 32.0, 12.0), 0, 0, 1.0, 0.0),
+    ("si64_transA", lambda: workloads.diamond(2), (20.0, 12.0, 24.0), 1, 0, -4.0, 0.0),
+    ("si64_transB", lambda: workloads.diamond(2), (12.0, 20.0, 16.0), 0, 1, 1.0, 0.0),
+    ("si64_beta", lambda: workloads.diamond(2), (12.0, 12.0, 16.0), 0, 0, 0.5, 2.0),
+    ("si8_images", lambda: workloads.diamond(1), (12.0, 8.0, 14.0), 0, 0, 1.0, 0.0),
+    ("jitter_rl16", lambda: workloads.diamond(2, jitter=0.1, seed=5), (16.0, 8.0, 24.0), 0, 0, 1.0, 0.0),
+    ("mixed_box", lambda: workloads.random_box(150, 15.0, 120, 13, 5, seed=3), (7.0, 6.0, 10.0), 0, 0, 1.0, 0.0),
+    ("mixed_box_tA", lambda: workloads.random_box(150, 15.0, 120, 13, 5, seed=3), (7.0, 6.0, 10.0), 1, 0, 1.0, 1.0),
+    ("open_ragged", lambda: workloads.random_cluster(61, 12.0, nfn=np.arange(61) % 7 + 1, seed=4), (6.0, 5.0, 7.0), 0, 0, 1.0, 0.0),
+    ("empty_output", lambda: workloads.diamond(1), (4.0, 4.0, 0.0), 0, 0, 1.0, 0.0),
+]
+
+
+def _rand(p, seed):
+    return np.random.default_rng(seed).normal(size=p.nval)
+
+
+@pytest.mark.parametrize("case", PRODUCT_CASES, ids=[c[0] for c in PRODUCT_CASES])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_product_parity(case, prec):
+    name, mk, (rA, rB, rC), tA, tB, alpha, beta = case
+    say(f"[product] {name} prec={prec} ranges={rA},{rB},{rC} tA={tA} tB={tB}")
+    s = mk()
+    gs = lsdm.System.from_workload(s)
+    gA, gB, gC = lsdm.Pattern(gs, rA), lsdm.Pattern(gs, rB), lsdm.Pattern(gs, rC)
+    oA, oB, oC = oracle.pattern(s, rA), oracle.pattern(s, rB), oracle.pattern(s, rC)
+    assert same_pattern(gA, oA) and same_pattern(gB, oB) and same_pattern(gC, oC)
+    a, b, c0 = _rand(oA, 1), _rand(oB, 2), _rand(oC, 3)
+    ref = oracle.multiply_op(oracle.Matrix(oA, a), tA, oracle.Matrix(oB, b), tB, oC).val * alpha + beta * c0
+    plan = lsdm.Plan(gA, tA, gB, tB, gC)
+    C = T(c0)
+    lsdm.multiply(plan, T(a), T(b), C, alpha=alpha, beta=beta, prec=prec)
+    got = C.cpu().numpy()
+    if prec == "fp64":
+        assert rel(got, ref) <= TOL64, rel(got, ref)
+    else:
+        # |fl(sum ab) - sum ab| <= gamma_n sum |a||b| with inputs rounded to fp32
+        absref = oracle.multiply_op(oracle.Matrix(oA, np.abs(a)), tA, oracle.Matrix(oB, np.abs(b)), tB, oC).val
+        n = 4 * int(np.diff(oA.row_ptr).max()) * 4 + 8   # summands per output element, generously
+        u = 2.0 ** -24
+        bound = abs(alpha) * (n + 2) * u / (1 - (n + 2) * u) * absref + 4 * u * np.abs(beta * c0) + 1e-30
+        assert np.all(np.abs(got - ref) <= bound + 4 * u * np.abs(ref))
+
+
+def test_product_adjoint_and_dot():
+    s = workloads.random_box(150, 15.0, 120, 13, 5, seed=8)
+    say("[adjoint] mixed_box")
+    gs = lsdm.System.from_workload(s)
+    rA, rB, rC = 7.0, 6.0, 9.0
+    gA, gB, gC = lsdm.Pattern(gs, rA), lsdm.Pattern(gs, rB), lsdm.Pattern(gs, rC)
+    oA, oB, oC = oracle.pattern(s, rA), oracle.pattern(s, rB), oracle.pattern(s, rC)
+    for tA, tB in ((0, 0), (1, 0), (0, 1), (1, 1)):
+        a, b, cb = _rand(oA, 1), _rand(oB, 2), _rand(oC, 3)
+        ab0, bb0 = _rand(oA, 4), _rand(oB, 5)
+        Ab, Bb = oracle.multiply_adjoint(oracle.Matrix(oA, a), tA, oracle.Matrix(oB, b), tB, oracle.Matrix(oC, cb))
+        plan = lsdm.Plan(gA, tA, gB, tB, gC)
+        gAb, gBb = T(ab0), T(bb0)
+        lsdm.multiply_adjoint(plan, T(cb), T(a), T(b), gAb, gBb)
+        assert rel(gAb.cpu().numpy(), Ab.val + ab0) <= TOL64
+        assert rel(gBb.cpu().numpy(), Bb.val + bb0) <= TOL64
+    a, b = _rand(oA, 6), _rand(oA, 7)
+    d = lsdm.dot(gA, T(a), T(b)).item()
+    assert abs(d - oracle.dot(a, b)) <= 1e-13 * np.sum(np.abs(a * b))
+
+
+# ---------------------------------------------------------------------------
+# the LNV chain
+# ---------------------------------------------------------------------------
+def _chain_setup(s, rS, rH, rL, seed=0):
+    gs = lsdm.System.from_workload(s)
+    lnv = lsdm.LNV(gs, rS, rH, rL)
+    p = lnv.patterns
+    vals = {w: gpu_values(p[w], s, w, seed=seed, rS=rS) for w in "LSH"}
+    return lnv, vals
+
+
+CHAIN_CASES = {
+    "config1_si64": lambda: (workloads.config(1)["system"], 8.0, 12.0, 12.0),
+    "si8_cell_images": lambda: (workloads.diamond(1), 8.0, 12.0, 12.0),
+    "si64_jitter_rl16": lambda: (workloads.diamond(2, jitter=0.1, seed=7), 8.0, 12.0, 16.0),
+    "mixed_box_13_5": lambda: (workloads.random_box(300, 17.5, 240, 13, 5, seed=2), 6.0, 8.0, 8.0),
+    "open_cluster_ragged": lambda: (workloads.random_cluster(90, 14.0, nfn=np.arange(90) % 5 + 1, seed=9), 5.0, 6.0, 6.5),
+}
+
+
+@pytest.mark.parametrize("name", list(CHAIN_CASES))
+def test_lnv_energy_grad_fp64(name):
+    s, rS, rH, rL = CHAIN_CASES[name]()
+    say(f"[lnv fp64] {name} atoms={s.n}")
+    lnv, v = _chain_setup(s, rS, rH, rL)
+    inp = oracle.make_inputs(s, rS, rH, rL)
+    for w in "LSH":
+        assert same_pattern(lnv.patterns[w], inp[w].pattern)
+        np.testing.assert_array_equal(v[w], inp[w].val)
+    ref = oracle.lnv_energy(inp["L"], inp["S"], inp["H"], rS, rH, rL)
+    G_ref = oracle.lnv_gradient(inp["L"], inp["S"], inp["H"], rS, rH, rL)
+    E, K = lnv.energy(T(v["L"]), T(v["S"]), T(v["H"]), want_K=True)
+    assert abs(E.item() - ref["E"]) <= TOL64 * abs(ref["E"]), (E.item(), ref["E"])
+    assert rel(K.cpu().numpy(), ref["K"].val) <= TOL64
+    E2, G = lnv.energy_grad(T(v["L"]), T(v["S"]), T(v["H"]))
+    assert E2.item() == E.item()
+    assert rel(G.cpu().numpy(), G_ref.val) <= TOL64, rel(G.cpu().numpy(), G_ref.val)
+
+
+def test_lnv_config2_fp64():
+    c = workloads.config(2)
+    s = c["system"]
+    say(f"[lnv fp64] config2 atoms={s.n}")
+    lnv, v = _chain_setup(s, c["rS"], c["rH"], c["rL"])
+    inp = oracle.make_inputs(s, c["rS"], c["rH"], c["rL"])
+    for w in "LSH":
+        assert same_pattern(lnv.patterns[w], inp[w].pattern)
+    ref = oracle.lnv_energy(inp["L"], inp["S"], inp["H"], c["rS"], c["rH"], c["rL"])
+    E, K = lnv.energy(T(v["L"]), T(v["S"]), T(v["H"]), want_K=True)
+    assert abs(E.item() - ref["E"]) <= TOL64 * abs(ref["E"])
+    assert rel(K.cpu().numpy(), ref["K"].val) <= TOL64
+    # gradient on sampled rows through the oracle's dependency cone
+    rows = np.array([0, 1, 777, 2048, 4095])
+    Gr = oracle.lnv_gradient(inp["L"], inp["S"], inp["H"], c["rS"], c["rH"], c["rL"], rows=rows)
+    _, G = lnv.energy_grad(T(v["L"]), T(v["S"]), T(v["H"]))
+    G = G.cpu().numpy()
+    p = inp["L"].pattern
+    for i in rows:
+        lo, hi = p.off[p.row_ptr[i]], p.off[p.row_ptr[i + 1] - 1] + 16
+        assert rel(G[lo:hi], oracle.row_slice(Gr, i)) <= TOL64
+
+
+def test_lnv_deterministic():
+    s, rS, rH, rL = CHAIN_CASES["mixed_box_13_5"]()
+    lnv, v = _chain_setup(s, rS, rH, rL)
+    out = []
+    for _ in range(2):
+        E, G = lnv.energy_grad(T(v["L"]), T(v["S"]), T(v["H"]))
+        out.append((E.cpu().numpy().copy(), G.cpu().numpy().copy()))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_autograd_function():
+    s, rS, rH, rL = CHAIN_CASES["si64_jitter_rl16"]()
+    lnv, v = _chain_setup(s, rS, rH, rL)
+    L = T(v["L"]).requires_grad_(True)
+    E = lsdm.LNVEnergy.apply(L, T(v["S"]), T(v["H"]), lnv, "fp64")
+    (3.0 * E).backward()
+    _, G = lnv.energy_grad(T(v["L"]), T(v["S"]), T(v["H"]))
+    assert torch.equal(L.grad, 3.0 * G)
