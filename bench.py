@@ -23,7 +23,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # MI355X dense matrix peaks
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "fp32_rc": 157.3}   # MI355X dense matrix peaks
 HBM_PEAK_GBS = 8000.0
 
 
@@ -89,16 +89,93 @@ def cpu_baseline(cfg, flops_per_atom):
             "seconds": round(dt, 3), "energy_per_atom": r["E"] / s.n}
 
 
+KERNEL_SRC = os.path.join(ROOT, "paper_0911_3584_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_si32768.json")
+
+
+def kernel_hash():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_per_step(prec):
+    """HBM bytes (fetch + write) of one step's product launches, from the
+    committed counter summary when it was taken on the current kernel source
+    and the same precision; None otherwise."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash() or t.get("prec") != prec or not t.get("dispatches"):
+        return None
+    per_step = t.get("steps", 1)
+    return round(sum(d["fetch_bytes"] + d["write_bytes"] for d in t["dispatches"]) / per_step, 0)
+
+
+def summarize_pmc(fetch_dir, write_dir, prec, out):
+    """Per-dispatch HBM bytes of the product kernels from two rocprofv3 --pmc
+    runs (FETCH_SIZE, WRITE_SIZE in KiB), scaled by what the same counters read
+    for the calibration copy (a torch copy of known size in the same run)."""
+    import csv
+    import glob
+
+    def rows(d):
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not f:
+            raise SystemExit(f"no counter_collection.csv under {d}")
+        return list(csv.DictReader(open(f[0])))
+
+    res = {}
+    for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        per = {}
+        for r in rows(d):
+            if r.get("Counter_Name") != name:
+                continue
+            per.setdefault(int(r["Dispatch_Id"]), [r["Kernel_Name"], 0.0])[1] += float(r["Counter_Value"])
+        res[name] = per
+    calib = None
+    for did, (kn, v) in sorted(res["FETCH_SIZE"].items()):
+        if "copy" in kn.lower() or "elementwise" in kn.lower():
+            if v > 900 * 1024:   # the 1 GiB calibration copy
+                calib = did
+                break
+    if calib is None:
+        raise SystemExit("calibration copy dispatch not found")
+    exp_kib = 1024 * 1024
+    f_fac = exp_kib / res["FETCH_SIZE"][calib][1]
+    w_fac = exp_kib / res["WRITE_SIZE"][calib][1]
+    prods = {}
+    for did, (kn, v) in res["FETCH_SIZE"].items():
+        if "k_prod" not in kn:
+            continue
+        w = res["WRITE_SIZE"].get(did, [kn, 0.0])[1]
+        prods[did] = (kn, v * f_fac * 1024, w * w_fac * 1024)
+    summ = {"kernel_hash": kernel_hash(), "prec": prec, "steps": 1, "fetch_scale": f_fac, "write_scale": w_fac,
+            "dispatches": [{"id": d, "kernel": k.split("(")[0], "fetch_bytes": f, "write_bytes": w}
+                           for d, (k, f, w) in sorted(prods.items())]}
+    with open(out, "w") as fh:
+        json.dump(summ, fh, indent=1)
+    print(f"wrote {out}: {len(prods)} product dispatches, fetch scale {f_fac:.3f}, write scale {w_fac:.3f}")
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-pmc":
+        # --summarize-pmc FETCH_DIR WRITE_DIR PREC [OUT]: the counter runs of one step
+        summarize_pmc(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5] if len(sys.argv) > 5 else TRAFFIC_FILE)
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", type=int, default=4)
-    ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32"])
-    ap.add_argument("--modes", default="fp64,fp32", help="modes to time; fp64 is the error reference")
+    ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16", "fp32_rc"])
+    ap.add_argument("--modes", default="fp64,fp32,bf16,fp32_rc", help="modes to time; fp64 is the error reference")
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one device copy of this size first (reference dispatch for HBM counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -124,6 +201,16 @@ def main():
     inp = make_inputs(lnv, sysm, cfg["rS"], "cuda:0")
     log(f"[bench] inputs {time.perf_counter() - t0:.1f} s")
 
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {args.calib_copy_mib} MiB read + {args.calib_copy_mib} MiB written")
+        del a, b
+
     modes = [m for m in args.modes.split(",") if m]
     if args.prec not in modes:
         modes.append(args.prec)
@@ -137,6 +224,9 @@ def main():
             res[m]["err_uHa_per_atom"] = 1e6 * abs(res[m]["E"] - res["fp64"]["E"]) / sysm.n
 
     prim = res[args.prec]
+    if args.profile_steps <= 0:
+        log("[bench] no profile steps: roofline not computed")
+        return
     rec = profile_mode(lnv, inp, args.prec, args.profile_steps)
     tot_ms = sum(v[0] for v in rec.values())
     tot_fl = sum(v[1] * v[2] for v in rec.values())
@@ -167,7 +257,8 @@ def main():
         "modes": {m: {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()} for m, r in res.items()},
         "roofline": {"kernel": f"k_prod_{args.prec} (all 8 product launches of a step)", "bound": "mfma",
                      "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": None, "per_product": per_product},
+                     "frac": round(achieved / peak, 4), "traffic": traffic_per_step(args.prec),
+                     "per_product": per_product},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, flops / sysm.n)

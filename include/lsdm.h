@@ -127,8 +127,8 @@ int lsdm_multiply(const lsdm_plan* plan, int prec, double alpha, const double* d
  * gradient dCbar on C's pattern,
  *   dAbar += P_A(Cbar op(B)^T)   (P_A(op(B) Cbar^T) when A enters transposed)
  *   dBbar += P_B(op(A)^T Cbar)   (P_B(Cbar^T op(A)) when B enters transposed)
- * Either output may be NULL (not computed).  Both accumulate.  FP64 and FP32
- * modes.  Errors: LSDM_EINVAL, LSDM_EUNSUPPORTED (other modes), LSDM_EDEVICE. */
+ * Either output may be NULL (not computed).  Both accumulate.  Every
+ * precision mode.  Errors: LSDM_EINVAL, LSDM_EDEVICE. */
 int lsdm_multiply_adjoint(const lsdm_plan* plan, int prec, const double* dCbar, const double* dA,
                           const double* dB, double* dAbar, double* dBbar, void* stream);
 
@@ -160,8 +160,8 @@ int lsdm_lnv_energy(lsdm_lnv* lnv, int prec, const double* dL, const double* dS,
 /* E as above and dGradL = dE/dL on L's pattern, the derivative of eq. 3 with
  * respect to each stored entry of L (blocks (i,j,n) and (j,i,-n) independent):
  *   6 (HLS + SLH) - 4 (HLSLS + SLHLS + SLSLH)
- * computed by the adjoint chain of the truncated products.  Modes FP64, FP32,
- * BF16 (the adjoint products then run in the same mode).  dGradL: device. */
+ * computed by the adjoint chain of the truncated products, in the same
+ * precision mode as the forward products.  dGradL: device. */
 int lsdm_lnv_energy_grad(lsdm_lnv* lnv, int prec, const double* dL, const double* dS, const double* dH,
                          double* dE, double* dGradL, void* stream);
 /* Kernel timing of the chain's products: with enable = 1 every product launch

@@ -60,6 +60,7 @@ class System:
         check(lib().lsdm_system_create(xyz.shape[0], _ptr(xyz), _ptr(nfn), None if lat is None else _ptr(lat),
                                        ctypes.byref(h)))
         self._h = h
+        self._destroy = lib().lsdm_system_destroy
         self.n = xyz.shape[0]
         self.nfn = nfn.copy()
 
@@ -69,7 +70,7 @@ class System:
 
     def __del__(self):
         if getattr(self, "_h", None):
-            lib().lsdm_system_destroy(self._h)
+            self._destroy(self._h)
             self._h = None
 
 
@@ -84,6 +85,7 @@ class Pattern:
             h = ctypes.c_void_p()
             check(lib().lsdm_pattern_create(system._h, float(R), ctypes.byref(h)))
             self._h, self._own = h, True
+            self._destroy = lib().lsdm_pattern_destroy
         nb, nv = ctypes.c_int64(), ctypes.c_int64()
         check(lib().lsdm_pattern_info(self._h, ctypes.byref(nb), ctypes.byref(nv)))
         self.n_blocks, self.n_values = nb.value, nv.value
@@ -107,7 +109,7 @@ class Pattern:
 
     def __del__(self):
         if getattr(self, "_own", False) and getattr(self, "_h", None):
-            lib().lsdm_pattern_destroy(self._h)
+            self._destroy(self._h)
             self._h = None
 
 
@@ -118,6 +120,7 @@ class Plan:
         h = ctypes.c_void_p()
         check(lib().lsdm_plan_create(A._h, int(transA), B._h, int(transB), C._h, ctypes.byref(h)))
         self._h = h
+        self._destroy = lib().lsdm_plan_destroy
         self.A, self.B, self.C = A, B, C
         nt, fl, nb = ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64()
         check(lib().lsdm_plan_info(h, ctypes.byref(nt), ctypes.byref(fl), ctypes.byref(nb)))
@@ -125,7 +128,7 @@ class Plan:
 
     def __del__(self):
         if getattr(self, "_h", None):
-            lib().lsdm_plan_destroy(self._h)
+            self._destroy(self._h)
             self._h = None
 
 
@@ -165,6 +168,7 @@ class LNV:
         h = ctypes.c_void_p()
         check(lib().lsdm_lnv_create(system._h, float(rS), float(rH), float(rL), ctypes.byref(h)))
         self._h = h
+        self._destroy = lib().lsdm_lnv_destroy
         self.system = system
         self.rS, self.rH, self.rL = rS, rH, rL
         self.patterns = {}
@@ -212,7 +216,7 @@ class LNV:
     def __del__(self):
         if getattr(self, "_h", None):
             self.patterns = {}
-            lib().lsdm_lnv_destroy(self._h)
+            self._destroy(self._h)
             self._h = None
 
 

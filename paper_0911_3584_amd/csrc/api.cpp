@@ -145,6 +145,69 @@ static void multiply_t(const lsdm_plan* pl, double alpha, const double* dA, cons
   HIP_CHECK(hipStreamSynchronize(st));   // the workspaces are released on return
 }
 
+static void multiply_bf16(const lsdm_plan* pl, double alpha, const double* dA, const double* dB, double beta,
+                          double* dC, hipStream_t st) {
+  typedef unsigned short u16;
+  DevBuf a32, b32, bt32, c32, a16, b16;
+  a32.alloc(strip_bytes(pl->A, 4));
+  b32.alloc(strip_bytes(pl->B, 4));
+  c32.alloc(strip_bytes(pl->C, 4));
+  a16.alloc(strip_bytes(pl->A, 2));
+  b16.alloc(strip_bytes(pl->B, 2));
+  fill<float>(a32.as<float>(), pl->A->n_strips * 64, 0.f, st);
+  fill<float>(b32.as<float>(), pl->B->n_strips * 64, 0.f, st);
+  fill<float>(c32.as<float>(), pl->C->n_strips * 64, 0.f, st);
+  user_to_strip<float>(pl->A, dA, a32.as<float>(), 1.0, st);
+  user_to_strip<float>(pl->B, dB, b32.as<float>(), 1.0, st);
+  // A: row-major copy, or for a transposed A the block-transposed copy of A
+  to_bf16(a32.as<float>(), pl->transA ? nullptr : a16.as<u16>(), pl->transA ? a16.as<u16>() : nullptr,
+          pl->A->n_strips * 64, st);
+  const float* bsrc = b32.as<float>();
+  if (pl->transB) {
+    bt32.alloc(strip_bytes(pl->B, 4));
+    transpose_strips<float>(pl->B, b32.as<float>(), bt32.as<float>(), st);
+    bsrc = bt32.as<float>();
+  }
+  to_bf16(bsrc, nullptr, b16.as<u16>(), pl->B->n_strips * 64, st);
+  if (beta != 0.0) user_to_strip<float>(pl->C, dC, c32.as<float>(), 1.0, st);
+  product_bf16(pl, a16.as<u16>(), b16.as<u16>(), c32.as<float>(), alpha, beta, st);
+  strip_to_user<float>(pl->C, c32.as<float>(), dC, st);
+  check_launch();
+  HIP_CHECK(hipStreamSynchronize(st));
+}
+
+// residual mode: FP64 master strips; FP32 product of the off-site parts; FP64
+// block-diagonal correction
+static void multiply_rc(const lsdm_plan* pl, double alpha, const double* dA, const double* dB, double beta, double* dC,
+                        hipStream_t st) {
+  DevBuf a64, b64, bt64, c64, a32, b32, rr;
+  a64.alloc(strip_bytes(pl->A, 8));
+  b64.alloc(strip_bytes(pl->B, 8));
+  c64.alloc(strip_bytes(pl->C, 8));
+  a32.alloc(strip_bytes(pl->A, 4));
+  b32.alloc(strip_bytes(pl->B, 4));
+  rr.alloc(strip_bytes(pl->C, 4));
+  fill<double>(a64.as<double>(), pl->A->n_strips * 64, 0.0, st);
+  fill<double>(b64.as<double>(), pl->B->n_strips * 64, 0.0, st);
+  fill<double>(c64.as<double>(), pl->C->n_strips * 64, 0.0, st);
+  user_to_strip<double>(pl->A, dA, a64.as<double>(), 1.0, st);
+  user_to_strip<double>(pl->B, dB, b64.as<double>(), 1.0, st);
+  const double* bsrc = b64.as<double>();
+  if (pl->transB) {
+    bt64.alloc(strip_bytes(pl->B, 8));
+    transpose_strips<double>(pl->B, b64.as<double>(), bt64.as<double>(), st);
+    bsrc = bt64.as<double>();
+  }
+  offsite_f32(pl->A, a64.as<double>(), a32.as<float>(), st);
+  offsite_f32(pl->B, bsrc, b32.as<float>(), st);
+  if (beta != 0.0) user_to_strip<double>(pl->C, dC, c64.as<double>(), 1.0, st);
+  product<float>(pl, a32.as<float>(), b32.as<float>(), rr.as<float>(), 1.0, 0.0, st);
+  rc_correct(pl, a64.as<double>(), bsrc, rr.as<float>(), c64.as<double>(), alpha, beta, st);
+  strip_to_user<double>(pl->C, c64.as<double>(), dC, st);
+  check_launch();
+  HIP_CHECK(hipStreamSynchronize(st));
+}
+
 // ---------------------------------------------------------------------------
 // the LNV chain
 // ---------------------------------------------------------------------------
@@ -269,6 +332,164 @@ static void lnv_backward(lsdm_lnv* L, double* dG, hipStream_t st) {
   check_launch();
 }
 
+// BF16 chain: bf16 operands, fp32 accumulation and fp32 master strips, K and E
+// in FP64.  Intermediates are rounded to bf16 once, when they become operands.
+enum { LR, LC, SC, HR, HC, XR, XC, MC, MbR, MbC, XbR };
+
+static void bf16_workspaces(lsdm_lnv* L) {
+  if (L->b16_ready) return;
+  const lsdm_pattern* who[11] = {L->pL, L->pL, L->pS, L->pH, L->pH, L->pX, L->pX, L->pM, L->pM, L->pM, L->pX};
+  for (int k = 0; k < 11; ++k) L->b16[k].alloc(strip_bytes(who[k], 2));
+  L->b16_ready = true;
+}
+
+static void chain_product_bf16(lsdm_lnv* L, int w, const unsigned short* A, const unsigned short* B, float* C,
+                               double alpha, double beta, hipStream_t st) {
+  if (!L->prof) {
+    product_bf16(chain_plan(L, w), A, B, C, alpha, beta, st);
+    return;
+  }
+  while (L->ev_pool.size() < L->ev_used + 2) {
+    hipEvent_t e;
+    HIP_CHECK(hipEventCreate(&e));
+    L->ev_pool.push_back(e);
+  }
+  HIP_CHECK(hipEventRecord(L->ev_pool[L->ev_used], st));
+  product_bf16(chain_plan(L, w), A, B, C, alpha, beta, st);
+  HIP_CHECK(hipEventRecord(L->ev_pool[L->ev_used + 1], st));
+  L->ev_used += 2;
+  L->ev_prod.push_back(w);
+}
+
+static void lnv_forward_bf16(lsdm_lnv* L, const double* dL, const double* dS, const double* dH, double* dK,
+                             double* dE, hipStream_t st) {
+  typedef unsigned short u16;
+  bf16_workspaces(L);
+  auto h = [&](int k) { return L->b16[k].as<u16>(); };
+  float* wL = L->wL.as<float>();
+  float* wS = L->wS.as<float>();
+  float* wH = L->wH.as<float>();
+  float* wX = L->wX.as<float>();
+  float* wM = L->wM.as<float>();
+  float* wP = L->wP.as<float>();
+  double* wH64 = L->wH64.as<double>();
+  double* wK = L->wK.as<double>();
+  fill<float>(wL, L->pL->n_strips * 64, 0.f, st);
+  fill<float>(wS, L->pS->n_strips * 64, 0.f, st);
+  fill<float>(wH, L->pH->n_strips * 64, 0.f, st);
+  fill<double>(wH64, L->pH->n_strips * 64, 0.0, st);
+  user_to_strip<float>(L->pL, dL, wL, 1.0, st);
+  user_to_strip<float>(L->pS, dS, wS, 1.0, st);
+  user_to_strip<float>(L->pH, dH, wH, 1.0, st);
+  user_to_strip<double>(L->pH, dH, wH64, 1.0, st);
+  to_bf16(wL, h(LR), h(LC), L->pL->n_strips * 64, st);
+  to_bf16(wS, nullptr, h(SC), L->pS->n_strips * 64, st);
+  to_bf16(wH, h(HR), h(HC), L->pH->n_strips * 64, st);
+  chain_product_bf16(L, 0, h(LR), h(SC), wX, 1.0, 0.0, st);    // X = LS
+  to_bf16(wX, h(XR), h(XC), L->pX->n_strips * 64, st);
+  chain_product_bf16(L, 1, h(XR), h(LC), wM, 1.0, 0.0, st);    // M = XL
+  to_bf16(wM, nullptr, h(MC), L->pM->n_strips * 64, st);
+  chain_product_bf16(L, 2, h(XR), h(MC), wP, 1.0, 0.0, st);    // P = XM on H's range
+  kassembly<float>(L, wM, wP, wK, st);
+  dot(wK, wH64, L->pH->n_strips * 64, 2.0, L->wE.as<double>(), dE, st);
+  if (dK) strip_to_user<double>(L->pH, wK, dK, st);
+  check_launch();
+}
+
+static void lnv_backward_bf16(lsdm_lnv* L, double* dG, hipStream_t st) {
+  typedef unsigned short u16;
+  auto h = [&](int k) { return L->b16[k].as<u16>(); };
+  float* wH = L->wH.as<float>();
+  float* wMb = L->wMb.as<float>();
+  float* wXb = L->wXb.as<float>();
+  float* wLb = L->wLb.as<float>();
+  fill<float>(wMb, L->pM->n_strips * 64, 0.f, st);
+  scatter_h<float>(L, wH, wMb, 6.0, st);
+  chain_product_bf16(L, 3, h(XC), h(HC), wMb, -4.0, 1.0, st);   // Mbar += X^T Pbar
+  to_bf16(wMb, h(MbR), h(MbC), L->pM->n_strips * 64, st);
+  chain_product_bf16(L, 4, h(HR), h(MC), wXb, -4.0, 0.0, st);   // Xbar = Pbar M
+  chain_product_bf16(L, 5, h(MbR), h(LC), wXb, 1.0, 1.0, st);   // Xbar += Mbar L
+  to_bf16(wXb, h(XbR), nullptr, L->pX->n_strips * 64, st);
+  chain_product_bf16(L, 6, h(XC), h(MbC), wLb, 1.0, 0.0, st);   // Lbar = X^T Mbar
+  chain_product_bf16(L, 7, h(XbR), h(SC), wLb, 1.0, 1.0, st);   // Lbar += Xbar S
+  strip_to_user<float>(L->pL, wLb, dG, st);
+  check_launch();
+}
+
+// Residual chain: every intermediate in FP64; each product is the FP32 product
+// of the off-site parts (timed as the chain's product) plus the FP64
+// block-diagonal correction.
+enum { RL, RS, RH, RX, RM, RMb, RXb };
+
+static void rc_workspaces(lsdm_lnv* L) {
+  if (L->rc_ready) return;
+  const lsdm_pattern* who[7] = {L->pL, L->pS, L->pH, L->pX, L->pM, L->pM, L->pX};
+  for (int k = 0; k < 7; ++k) L->r32[k].alloc(strip_bytes(who[k], 4));
+  L->rr32.alloc(strip_bytes(L->pM, 4));
+  L->rc_ready = true;
+}
+
+static void rc_step(lsdm_lnv* L, int w, const double* A64, const float* A32, const double* B64, const float* B32,
+                    double* C64, double alpha, double beta, hipStream_t st) {
+  float* rr = L->rr32.as<float>();
+  chain_product<float>(L, w, A32, B32, rr, 1.0, 0.0, st);
+  rc_correct(chain_plan(L, w), A64, B64, rr, C64, alpha, beta, st);
+}
+
+static void lnv_forward_rc(lsdm_lnv* L, const double* dL, const double* dS, const double* dH, double* dK, double* dE,
+                           hipStream_t st) {
+  rc_workspaces(L);
+  auto r = [&](int k) { return L->r32[k].as<float>(); };
+  double* wL = L->wL.as<double>();
+  double* wS = L->wS.as<double>();
+  double* wH = L->wH64.as<double>();
+  double* wX = L->wX.as<double>();
+  double* wM = L->wM.as<double>();
+  double* wP = L->wP.as<double>();
+  double* wK = L->wK.as<double>();
+  fill<double>(wL, L->pL->n_strips * 64, 0.0, st);
+  fill<double>(wS, L->pS->n_strips * 64, 0.0, st);
+  fill<double>(wH, L->pH->n_strips * 64, 0.0, st);
+  user_to_strip<double>(L->pL, dL, wL, 1.0, st);
+  user_to_strip<double>(L->pS, dS, wS, 1.0, st);
+  user_to_strip<double>(L->pH, dH, wH, 1.0, st);
+  offsite_f32(L->pL, wL, r(RL), st);
+  offsite_f32(L->pS, wS, r(RS), st);
+  offsite_f32(L->pH, wH, r(RH), st);
+  rc_step(L, 0, wL, r(RL), wS, r(RS), wX, 1.0, 0.0, st);       // X = LS
+  offsite_f32(L->pX, wX, r(RX), st);
+  rc_step(L, 1, wX, r(RX), wL, r(RL), wM, 1.0, 0.0, st);       // M = XL
+  offsite_f32(L->pM, wM, r(RM), st);
+  rc_step(L, 2, wX, r(RX), wM, r(RM), wP, 1.0, 0.0, st);       // P = XM on H's range
+  kassembly<double>(L, wM, wP, wK, st);
+  dot(wK, wH, L->pH->n_strips * 64, 2.0, L->wE.as<double>(), dE, st);
+  if (dK) strip_to_user<double>(L->pH, wK, dK, st);
+  check_launch();
+}
+
+static void lnv_backward_rc(lsdm_lnv* L, double* dG, hipStream_t st) {
+  auto r = [&](int k) { return L->r32[k].as<float>(); };
+  double* wL = L->wL.as<double>();
+  double* wS = L->wS.as<double>();
+  double* wH = L->wH64.as<double>();
+  double* wX = L->wX.as<double>();
+  double* wM = L->wM.as<double>();
+  double* wMb = L->wMb.as<double>();
+  double* wXb = L->wXb.as<double>();
+  double* wLb = L->wLb.as<double>();
+  fill<double>(wMb, L->pM->n_strips * 64, 0.0, st);
+  scatter_h<double>(L, wH, wMb, 6.0, st);
+  rc_step(L, 3, wX, r(RX), wH, r(RH), wMb, -4.0, 1.0, st);     // Mbar += X^T Pbar
+  offsite_f32(L->pM, wMb, r(RMb), st);
+  rc_step(L, 4, wH, r(RH), wM, r(RM), wXb, -4.0, 0.0, st);     // Xbar = Pbar M
+  rc_step(L, 5, wMb, r(RMb), wL, r(RL), wXb, 1.0, 1.0, st);    // Xbar += Mbar L
+  offsite_f32(L->pX, wXb, r(RXb), st);
+  rc_step(L, 6, wX, r(RX), wMb, r(RMb), wLb, 1.0, 0.0, st);    // Lbar = X^T Mbar
+  rc_step(L, 7, wXb, r(RXb), wS, r(RS), wLb, 1.0, 1.0, st);    // Lbar += Xbar S
+  strip_to_user<double>(L->pL, wLb, dG, st);
+  check_launch();
+}
+
 }  // namespace lsdm
 
 lsdm_lnv::~lsdm_lnv() {
@@ -357,7 +578,7 @@ int lsdm_plan_info(const lsdm_plan* pl, int64_t* n_triples, double* flops, int64
     if (!pl) LSDM_THROW(LSDM_EINVAL, "null plan");
     if (n_triples) *n_triples = pl->n_triples;
     if (flops) *flops = pl->flops;
-    if (plan_bytes) *plan_bytes = (int64_t)(pl->d_tiles.bytes + pl->d_steps.bytes);
+    if (plan_bytes) *plan_bytes = (int64_t)(pl->n_tiles * sizeof(Tile) + pl->n_steps * sizeof(Step));
   });
 }
 
@@ -372,7 +593,9 @@ int lsdm_multiply(const lsdm_plan* pl, int prec, double alpha, const double* dA,
     hipStream_t st = (hipStream_t)stream;
     if (prec == LSDM_FP64) multiply_t<double>(pl, alpha, dA, dB, beta, dC, st);
     else if (prec == LSDM_FP32) multiply_t<float>(pl, alpha, dA, dB, beta, dC, st);
-    else LSDM_THROW(LSDM_EUNSUPPORTED, "precision mode not available for lsdm_multiply");
+    else if (prec == LSDM_BF16) multiply_bf16(pl, alpha, dA, dB, beta, dC, st);
+    else if (prec == LSDM_FP32_RC) multiply_rc(pl, alpha, dA, dB, beta, dC, st);
+    else LSDM_THROW(LSDM_EINVAL, "unknown precision mode");
   });
 }
 
@@ -381,11 +604,13 @@ int lsdm_multiply_adjoint(const lsdm_plan* pl, int prec, const double* dCbar, co
   return guarded([&] {
     require_device();
     if (!pl || !dCbar || !dA || !dB) LSDM_THROW(LSDM_EINVAL, "null argument");
-    if (prec != LSDM_FP64 && prec != LSDM_FP32) LSDM_THROW(LSDM_EUNSUPPORTED, "adjoint supports FP64 and FP32");
+    if (prec < LSDM_FP64 || prec > LSDM_FP32_RC) LSDM_THROW(LSDM_EINVAL, "unknown precision mode");
     hipStream_t st = (hipStream_t)stream;
     auto run = [&](const lsdm_plan* q, const double* x, const double* y, double* out) {
       if (prec == LSDM_FP64) multiply_t<double>(q, 1.0, x, y, 1.0, out, st);
-      else multiply_t<float>(q, 1.0, x, y, 1.0, out, st);
+      else if (prec == LSDM_FP32) multiply_t<float>(q, 1.0, x, y, 1.0, out, st);
+      else if (prec == LSDM_BF16) multiply_bf16(q, 1.0, x, y, 1.0, out, st);
+      else multiply_rc(q, 1.0, x, y, 1.0, out, st);
     };
     if (dAbar) {
       // Abar += P_A(Cbar op(B)^T), or P_A(op(B) Cbar^T) when A enters transposed
@@ -470,7 +695,9 @@ int lsdm_lnv_energy(lsdm_lnv* L, int prec, const double* dL, const double* dS, c
     hipStream_t st = (hipStream_t)stream;
     if (prec == LSDM_FP64) lnv_forward<double>(L, dL, dS, dH, dK, dE, st);
     else if (prec == LSDM_FP32) lnv_forward<float>(L, dL, dS, dH, dK, dE, st);
-    else LSDM_THROW(LSDM_EUNSUPPORTED, "precision mode not available");
+    else if (prec == LSDM_BF16) lnv_forward_bf16(L, dL, dS, dH, dK, dE, st);
+    else if (prec == LSDM_FP32_RC) lnv_forward_rc(L, dL, dS, dH, dK, dE, st);
+    else LSDM_THROW(LSDM_EINVAL, "unknown precision mode");
   });
 }
 
@@ -486,8 +713,14 @@ int lsdm_lnv_energy_grad(lsdm_lnv* L, int prec, const double* dL, const double* 
     } else if (prec == LSDM_FP32) {
       lnv_forward<float>(L, dL, dS, dH, nullptr, dE, st);
       lnv_backward<float>(L, dG, st);
+    } else if (prec == LSDM_BF16) {
+      lnv_forward_bf16(L, dL, dS, dH, nullptr, dE, st);
+      lnv_backward_bf16(L, dG, st);
+    } else if (prec == LSDM_FP32_RC) {
+      lnv_forward_rc(L, dL, dS, dH, nullptr, dE, st);
+      lnv_backward_rc(L, dG, st);
     } else {
-      LSDM_THROW(LSDM_EUNSUPPORTED, "precision mode not available");
+      LSDM_THROW(LSDM_EINVAL, "unknown precision mode");
     }
   });
 }

@@ -1,10 +1,14 @@
 // Launchers of the HIP kernels (kernels.hip).
 #pragma once
 #include "lsdm_internal.h"
+#include "plan_common.h"
 
 namespace lsdm {
 
 constexpr int DOT_BLOCKS = 1024;   // fixed grid of the reproducible dot
+
+// layout maps of a pattern (built on first use; symbolic.cpp)
+void ensure_maps(lsdm_pattern* p);
 
 template <class T> void fill(T* p, i64 n, T v, hipStream_t st);
 template <class T> void user_to_strip(const lsdm_pattern* p, const double* user, T* strip, double scale, hipStream_t st);
@@ -12,6 +16,19 @@ template <class T> void strip_to_user(const lsdm_pattern* p, const T* strip, dou
 template <class T> void transpose_strips(const lsdm_pattern* p, const T* in, T* out, hipStream_t st);
 // C = alpha P_C(op(A) B) + beta C in strip layout (B already transposed if the plan says so)
 template <class T> void product(const lsdm_plan* pl, const T* A, const T* B, T* C, double alpha, double beta, hipStream_t st);
+// symbolic pass on the GPU: steps of a plan (count pass fill = 0, fill pass fill = 1)
+void plan_steps(const Tile* tiles, i64 ntiles, const KEnt* kent, const i64* kbeg, const PlanView& v, int fill,
+                i32* counts, Step* steps, unsigned long long* work);
+// residual mode: fp32 copy of the off-site part; FP64 correction
+// C = alpha (RR + D_A B + A D_B - D_A D_B) + beta C with RR = P_C(R_A R_B) in fp32
+void offsite_f32(const lsdm_pattern* p, const double* in, float* out, hipStream_t st);
+void rc_correct(const lsdm_plan* pl, const double* A64, const double* B64, const float* RR, double* C64, double alpha,
+                double beta, hipStream_t st);
+// BF16 path: fp32 strips -> bf16 copies (row-major R and/or block-transposed C)
+void to_bf16(const float* in, unsigned short* outR, unsigned short* outC, i64 n, hipStream_t st);
+// C (fp32) = alpha P_C(op(A) B) + beta C with bf16 operands (A: R copy, or C copy of X when transposed; B: C copy)
+void product_bf16(const lsdm_plan* pl, const unsigned short* A, const unsigned short* B, float* C, double alpha,
+                  double beta, hipStream_t st);
 template <class T> void kassembly(const lsdm_lnv* L, const T* M, const T* P, double* K, hipStream_t st);
 template <class T> void scatter_h(const lsdm_lnv* L, const T* H, T* Mb, double scale, hipStream_t st);
 // out[0] = scale * sum a[i] b[i]; partial holds 2 * DOT_BLOCKS doubles

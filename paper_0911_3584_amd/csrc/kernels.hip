@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
+#include "plan_common.h"
 
 namespace lsdm {
 
@@ -73,123 +74,643 @@ __global__ void k_transpose_strips(const T* __restrict__ in, T* __restrict__ out
 }
 
 // ---------------------------------------------------------------------------
-// truncated block product, FP64: v_mfma_f64_4x4x4_4b_f64
+// truncated block product C = alpha P_C(op(A) B) + beta C
+//
+// One wavefront per tile of 4 output rows x TJ output column quads; slot
+// (i, jq) accumulates the output strip (row i, column quad jq).  Each step of
+// the tile is one inner pseudo-atom k: up to 4 blocks A_{i,k} and TJ strips
+// B_{k,jq}, and a mask of the slots with useful work.  Step records are
+// wave-uniform (scalar loads); the next step's record and operands are loaded
+// while the current step's MFMAs issue.
+//
+// FP64: v_mfma_f64_4x4x4_4b_f64, the 4 blocks of one instruction are the 4
+//   column blocks t of the strip; A_{i,k} is replicated over them.
+// FP32: v_mfma_f32_4x4x1_16b_f32, the 16 blocks are (t, kk) pairs b = 4t + kk,
+//   each holding the rank-1 term of one inner index kk; the 4 partials are
+//   summed across lanes in the epilogue, after which lane l holds element l of
+//   the output strip.
 // ---------------------------------------------------------------------------
-template <bool TA>
-__global__ void __launch_bounds__(256) k_prod_f64(const Tile* __restrict__ tiles, i64 ntiles,
-                                                  const Step* __restrict__ steps, const double* __restrict__ A,
-                                                  const double* __restrict__ B, double* __restrict__ C,
-                                                  const uint8_t* __restrict__ cmask, double alpha, double beta) {
+template <class T> struct Mma;
+template <> struct Mma<double> {
+  typedef double acc_t;
+  static __device__ __forceinline__ acc_t zero() { return 0.0; }
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mma<float> {
+  typedef f4 acc_t;
+  static __device__ __forceinline__ acc_t zero() { return f4{0.f, 0.f, 0.f, 0.f}; }
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
+  }
+};
+
+// a step record lives in two lanes of a batch of 32 records (8 dwords per lane)
+__device__ __forceinline__ int rec_field(const int (&batch)[8], int r, int d) {
+  return __builtin_amdgcn_readlane(batch[d & 7], 2 * r + (d >> 3));
+}
+
+template <class T, bool TA>
+__global__ void __launch_bounds__(256) k_prod(const Tile* __restrict__ tiles, i64 ntiles,
+                                              const Step* __restrict__ steps, const T* __restrict__ A,
+                                              const T* __restrict__ B, T* __restrict__ C,
+                                              const uint8_t* __restrict__ cmask, T alpha, T beta) {
+  typedef typename Mma<T>::acc_t acc_t;
+  constexpr bool F64 = sizeof(T) == 8;
+  constexpr int RB = 32;   // step records per batch
   const int lane = threadIdx.x & 63;
-  const i64 wave0 = uniform64((i64)blockIdx.x * 4 + (threadIdx.x >> 6));
-  const i64 nw = (i64)gridDim.x * 4;
-  const int kk = lane >> 4, blk = (lane >> 2) & 3, x = lane & 3;
-  // operand A[b][x][kk] = A_ik[x][kk]; transposed: (X_ki)^T[x][kk] = X_ki[kk][x]
+  const int wave = threadIdx.x >> 6;
+  // XCD-aware mapping: workgroups are dealt round-robin to the 8 XCDs, so give
+  // each XCD a contiguous range of tiles (neighbouring tiles share operands
+  // through that XCD's L2)
+  const int nx = 8;
+  const int xcd = blockIdx.x % nx;
+  const i64 lb = blockIdx.x / nx;
+  const i64 nb_x = (gridDim.x - xcd + nx - 1) / nx;
+  const i64 chunk = (ntiles + nx - 1) / nx;
+  const i64 t_begin = (i64)xcd * chunk;
+  const i64 t_end = t_begin + chunk < ntiles ? t_begin + chunk : ntiles;
+  // FP64: lane = 16 kk + 4 blk + x.  FP32: lane = 16 t + 4 kk + x.
+  const int x = lane & 3;
+  const int kk = F64 ? (lane >> 4) : ((lane >> 2) & 3);
   const int a_off = TA ? (kk * 4 + x) : (x * 4 + kk);
-  // operand B[b][kk][x] = block b of the strip, element [kk][x]; the result
-  // D[b][r][c] sits in lane 16r + 4b + c, which is the same offset
-  const int b_off = blk * 16 + kk * 4 + x;
-  for (i64 t = wave0; t < ntiles; t += nw) {
-    const Tile* tp = tiles + t;
+  const int b_off = F64 ? (((lane >> 2) & 3) * 16 + (lane >> 4) * 4 + x) : lane;
+  const int* sw = reinterpret_cast<const int*>(steps);
+  for (i64 t = t_begin + lb * 4 + wave; t < t_end; t += nb_x * 4) {
+    const Tile* tp = tiles + uniform64(t);
     const i64 s0 = tp->step0;
     const int ns = tp->nsteps;
-    double acc[16];
+    acc_t acc[4 * TJ];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-    for (int s = 0; s < ns; ++s) {
-      const Step* sp = steps + s0 + s;
-      const uint32_t mask = sp->mask;
-      double av[4], bv[4];
+    for (int q = 0; q < 4 * TJ; ++q) acc[q] = Mma<T>::zero();
+    if (ns > 0) {
+      // records of steps [s0 + RB*b, s0 + RB*(b+1)): lane l holds dwords 8l..8l+7
+      // (the step array is padded by one batch, so the last batch may overrun)
+      int cur[8], nxt[8];
+      {
+        const int* src = sw + (s0 * 16) + 8 * lane;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) cur[e] = src[e];
+      }
+      // operands of step 0
+      T av[4], bv[TJ];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const i32 a = sp->a[i];
-        av[i] = a >= 0 ? A[(i64)a * 16 + a_off] : 0.0;
+        const T* Ab = A + (i64)max(rec_field(cur, 0, i), 0) * 16;
+        av[i] = Ab[a_off];
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const i32 b = sp->b[j];
-        bv[j] = b >= 0 ? B[(i64)b * 64 + b_off] : 0.0;
+      for (int j = 0; j < TJ; ++j) {
+        const T* Bb = B + (i64)max(rec_field(cur, 0, 4 + j), 0) * 64;
+        bv[j] = Bb[b_off];
       }
+      uint32_t mask = (uint32_t)rec_field(cur, 0, 4 + TJ);
+      const int nbatch = (ns + RB - 1) / RB;
+      for (int b = 0; b < nbatch; ++b) {
+        {
+          const int* src = sw + (s0 + (i64)RB * (b + 1)) * 16 + 8 * lane;
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+          for (int e = 0; e < 8; ++e) nxt[e] = src[e];
+        }
+        const int rend = (ns - RB * b) < RB ? (ns - RB * b) : RB;
+        for (int r = 0; r < rend; ++r) {
+          // record of step s+1: in this batch, or the first of the next
+          int ra[4], rb[TJ];
+          uint32_t nmask;
+          if (r + 1 < RB) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (mask >> (4 * i + j) & 1u) acc[4 * i + j] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[i], bv[j], acc[4 * i + j], 0, 0, 0);
+            for (int i = 0; i < 4; ++i) ra[i] = rec_field(cur, r + 1, i);
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) rb[j] = rec_field(cur, r + 1, 4 + j);
+            nmask = (uint32_t)rec_field(cur, r + 1, 4 + TJ);
+          } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ra[i] = rec_field(nxt, 0, i);
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) rb[j] = rec_field(nxt, 0, 4 + j);
+            nmask = (uint32_t)rec_field(nxt, 0, 4 + TJ);
+          }
+          if (RB * b + r + 1 >= ns) nmask = 0u;
+          // operands of step s+1 (unconditional: absent operands read block 0,
+          // their slots are masked off)
+          T nav[4], nbv[TJ];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const T* Ab = A + (i64)max(ra[i], 0) * 16;
+            nav[i] = Ab[a_off];
+          }
+#pragma unroll
+          for (int j = 0; j < TJ; ++j) {
+            const T* Bb = B + (i64)max(rb[j], 0) * 64;
+            nbv[j] = Bb[b_off];
+          }
+          // MFMAs of step s
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < TJ; ++j)
+              if (mask >> (TJ * i + j) & 1u) acc[TJ * i + j] = Mma<T>::mma(av[i], bv[j], acc[TJ * i + j]);
+          mask = nmask;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) av[i] = nav[i];
+#pragma unroll
+          for (int j = 0; j < TJ; ++j) bv[j] = nbv[j];
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) cur[e] = nxt[e];
+      }
     }
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < 4 * TJ; ++q) {
       const i32 cs = tp->cstrip[q];
       if (cs < 0) continue;
+      T val;
+      int blk;
+      if constexpr (F64) {
+        val = acc[q];
+        blk = (lane >> 2) & 3;
+      } else {
+        f4 v = acc[q];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          v[e] += __shfl_xor(v[e], 4);
+          v[e] += __shfl_xor(v[e], 8);
+        }
+        val = kk == 0 ? v[0] : kk == 1 ? v[1] : kk == 2 ? v[2] : v[3];
+        blk = lane >> 4;
+      }
       const bool keep = (cmask[cs] >> blk) & 1;
       const i64 idx = (i64)cs * 64 + b_off;
-      double v = keep ? alpha * acc[q] : 0.0;
-      if (beta != 0.0) v += beta * C[idx];
-      C[idx] = v;
+      T o = keep ? alpha * val : (T)0;
+      if (beta != (T)0) o += beta * C[idx];
+      C[idx] = o;
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// truncated block product, FP32: v_mfma_f32_4x4x1_16b_f32.  The 16 blocks of
-// one instruction are (column block t, inner index kk) pairs b = 4t + kk; each
-// holds the rank-1 term of one kk, and the 4 partials are summed across lanes
-// at the end of the tile.  Lane l then loads and stores element l of a strip.
+// The same plans on the dense 16x16x4 MFMA: one instruction per active
+// column quad covers the 4 rows of the tile at once (rows without an A block
+// contribute zeros).  Fewer load and MFMA instructions per useful triple when
+// most rows of a step are active; more wasted lanes when few are.
+//   f32 16x16x4: lane l holds A[l%16][l/16] and B[l/16][l%16]; D[4(l/16)+v][l%16]
+//   f64 16x16x4: same A and B; D[4v + l/16][l%16]          (measured on gfx950)
 // ---------------------------------------------------------------------------
-template <bool TA>
-__global__ void __launch_bounds__(256) k_prod_f32(const Tile* __restrict__ tiles, i64 ntiles,
-                                                  const Step* __restrict__ steps, const float* __restrict__ A,
-                                                  const float* __restrict__ B, float* __restrict__ C,
-                                                  const uint8_t* __restrict__ cmask, float alpha, float beta) {
+template <class T> struct Mma16;
+template <> struct Mma16<double> {
+  typedef d4 acc_t;
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mma16<float> {
+  typedef f4 acc_t;
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+template <class T, bool TA>
+__global__ void __launch_bounds__(256) k_prod16(const Tile* __restrict__ tiles, i64 ntiles,
+                                                const Step* __restrict__ steps, const T* __restrict__ A,
+                                                const T* __restrict__ B, T* __restrict__ C,
+                                                const uint8_t* __restrict__ cmask, T alpha, T beta) {
+  typedef typename Mma16<T>::acc_t acc_t;
+  constexpr bool F64 = sizeof(T) == 8;
+  constexpr int RB = 32;
   const int lane = threadIdx.x & 63;
-  const i64 wave0 = uniform64((i64)blockIdx.x * 4 + (threadIdx.x >> 6));
-  const i64 nw = (i64)gridDim.x * 4;
-  const int x = lane & 3, kk = (lane >> 2) & 3, t4 = lane >> 4;
-  const int a_off = TA ? (kk * 4 + x) : (x * 4 + kk);
-  for (i64 t = wave0; t < ntiles; t += nw) {
-    const Tile* tp = tiles + t;
+  const int wave = threadIdx.x >> 6;
+  const int nx = 8;
+  const int xcd = blockIdx.x % nx;
+  const i64 lb = blockIdx.x / nx;
+  const i64 nb_x = (gridDim.x - xcd + nx - 1) / nx;
+  const i64 chunk = (ntiles + nx - 1) / nx;
+  const i64 t_begin = (i64)xcd * chunk;
+  const i64 t_end = t_begin + chunk < ntiles ? t_begin + chunk : ntiles;
+  // A operand: row = l % 16 (tile row i = row / 4, block row r = row % 4), inner kk = l / 16
+  const int arow = lane & 15, ai = arow >> 2, ar = arow & 3, kk = lane >> 4;
+  const int a_off = TA ? (kk * 4 + ar) : (ar * 4 + kk);
+  // B operand: inner kk = l / 16, column = l % 16 (block t = col / 4, c = col % 4)
+  const int b_off = ((lane & 15) >> 2) * 16 + kk * 4 + (lane & 3);
+  const int* sw = reinterpret_cast<const int*>(steps);
+  for (i64 t = t_begin + lb * 4 + wave; t < t_end; t += nb_x * 4) {
+    const Tile* tp = tiles + uniform64(t);
     const i64 s0 = tp->step0;
     const int ns = tp->nsteps;
-    f4 acc[16];
+    acc_t acc[TJ];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int s = 0; s < ns; ++s) {
-      const Step* sp = steps + s0 + s;
-      const uint32_t mask = sp->mask;
-      float av[4], bv[4];
+    for (int q = 0; q < TJ; ++q)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const i32 a = sp->a[i];
-        av[i] = a >= 0 ? A[(i64)a * 16 + a_off] : 0.f;
+      for (int e = 0; e < 4; ++e) acc[q][e] = (T)0;
+    if (ns > 0) {
+      int cur[8], nxt[8];
+      {
+        const int* src = sw + (s0 * 16) + 8 * lane;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) cur[e] = src[e];
       }
+      auto a_load = [&](int a0, int a1, int a2, int a3) -> T {
+        const int a = ai == 0 ? a0 : ai == 1 ? a1 : ai == 2 ? a2 : a3;
+        const T v = A[(i64)max(a, 0) * 16 + a_off];
+        return a >= 0 ? v : (T)0;
+      };
+      T av = a_load(rec_field(cur, 0, 0), rec_field(cur, 0, 1), rec_field(cur, 0, 2), rec_field(cur, 0, 3));
+      T bv[TJ];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const i32 b = sp->b[j];
-        bv[j] = b >= 0 ? B[(i64)b * 64 + lane] : 0.f;
+      for (int j = 0; j < TJ; ++j) bv[j] = B[(i64)max(rec_field(cur, 0, 4 + j), 0) * 64 + b_off];
+      uint32_t mask = (uint32_t)rec_field(cur, 0, 4 + TJ);
+      const int nbatch = (ns + RB - 1) / RB;
+      for (int b = 0; b < nbatch; ++b) {
+        {
+          const int* src = sw + (s0 + (i64)RB * (b + 1)) * 16 + 8 * lane;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) nxt[e] = src[e];
+        }
+        const int rend = (ns - RB * b) < RB ? (ns - RB * b) : RB;
+        for (int r = 0; r < rend; ++r) {
+          int ra[4], rb[TJ];
+          uint32_t nmask;
+          if (r + 1 < RB) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ra[i] = rec_field(cur, r + 1, i);
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) rb[j] = rec_field(cur, r + 1, 4 + j);
+            nmask = (uint32_t)rec_field(cur, r + 1, 4 + TJ);
+          } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ra[i] = rec_field(nxt, 0, i);
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) rb[j] = rec_field(nxt, 0, 4 + j);
+            nmask = (uint32_t)rec_field(nxt, 0, 4 + TJ);
+          }
+          if (RB * b + r + 1 >= ns) nmask = 0u;
+          const T nav = a_load(ra[0], ra[1], ra[2], ra[3]);
+          T nbv[TJ];
+#pragma unroll
+          for (int j = 0; j < TJ; ++j) nbv[j] = B[(i64)max(rb[j], 0) * 64 + b_off];
+          // column quad jq is active when any row's slot (i, jq) is
+#pragma unroll
+          for (int j = 0; j < TJ; ++j) {
+            const uint32_t colbits = (mask >> j) & (1u | (1u << TJ) | (1u << (2 * TJ)) | (1u << (3 * TJ)));
+            if (colbits) acc[j] = Mma16<T>::mma(av, bv[j], acc[j]);
+          }
+          mask = nmask;
+          av = nav;
+#pragma unroll
+          for (int j = 0; j < TJ; ++j) bv[j] = nbv[j];
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) cur[e] = nxt[e];
       }
+    }
+    // epilogue: lane l, register v holds D[row][col]; f32 row = 4 (l/16) + v,
+    // f64 row = 4 v + l/16; col = l % 16 (block t = col / 4, c = col % 4)
+    const int col = lane & 15, tb = col >> 2, cc = col & 3;
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = F64 ? (4 * v + (lane >> 4)) : (4 * (lane >> 4) + v);
+        const int i = row >> 2, rr = row & 3;
+        const i32 c0 = tp->cstrip[j], c1 = tp->cstrip[TJ + j], c2 = tp->cstrip[2 * TJ + j], c3 = tp->cstrip[3 * TJ + j];
+        const i32 cs = i == 0 ? c0 : i == 1 ? c1 : i == 2 ? c2 : c3;
+        if (cs < 0) continue;
+        const bool keep = (cmask[cs] >> tb) & 1;
+        const i64 idx = (i64)cs * 64 + tb * 16 + rr * 4 + cc;
+        T o = keep ? alpha * acc[j][v] : (T)0;
+        if (beta != (T)0) o += beta * C[idx];
+        C[idx] = o;
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// BF16 products: v_mfma_f32_4x4x4_16b_bf16.  Lane l = 4b + x holds 4 bf16 of
+// A[b][x][0..3] (a row) and of B[b][0..3][x] (a column); D[b][r][c] is in lane
+// 4b + c, register r (measured on gfx950).  The 16 blocks of one instruction
+// are the 4 column quads of a group (g = l >> 4) times the 4 blocks of a strip
+// (t = (l >> 2) & 3), all against the same A_{i,k}, with the full inner
+// dimension 4 in one instruction.  Operand copies: A in row-major blocks ("R"),
+// or for a transposed A the column-major copy ("C") of X, whose column x of
+// X_{k,i} is row x of A_{i,k}; B always in column-major blocks.  FP32
+// accumulation, FP32 output strips (row-major) with alpha, beta.
+// ---------------------------------------------------------------------------
+typedef short s4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short bf16_rne(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest even (finite inputs)
+  return (unsigned short)(u >> 16);
+}
+
+// fp32 strips -> bf16 copies: R keeps the layout, C transposes every 4x4 block
+__global__ void k_to_bf16(const float* __restrict__ in, unsigned short* __restrict__ outR,
+                          unsigned short* __restrict__ outC, i64 n) {
+  for (i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x; g < n; g += (i64)gridDim.x * blockDim.x) {
+    const unsigned short v = bf16_rne(in[g]);
+    if (outR) outR[g] = v;
+    if (outC) {
+      const int e = (int)(g & 15), r = e >> 2, c = e & 3;
+      outC[(g & ~(i64)15) + c * 4 + r] = v;
+    }
+  }
+}
+
+template <bool TA>
+__global__ void __launch_bounds__(256) k_prod_bf16(const Tile* __restrict__ tiles, i64 ntiles,
+                                                   const Step* __restrict__ steps,
+                                                   const unsigned short* __restrict__ A,
+                                                   const unsigned short* __restrict__ B, float* __restrict__ C,
+                                                   const uint8_t* __restrict__ cmask, float alpha, float beta) {
+  static_assert(TJ % 4 == 0, "column quads come in groups of 4");
+  constexpr int NG = TJ / 4;
+  constexpr int RB = 32;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int nx = 8;
+  const int xcd = blockIdx.x % nx;
+  const i64 lb = blockIdx.x / nx;
+  const i64 nb_x = (gridDim.x - xcd + nx - 1) / nx;
+  const i64 chunk = (ntiles + nx - 1) / nx;
+  const i64 t_begin = (i64)xcd * chunk;
+  const i64 t_end = t_begin + chunk < ntiles ? t_begin + chunk : ntiles;
+  const int x = lane & 3, tb = (lane >> 2) & 3, g = lane >> 4;
+  const int a_off = x * 4;             // row x of A_ik (R copy) = column x of X_ki (C copy)
+  const int b_off = tb * 16 + x * 4;   // column x of block tb (C copy)
+  const int* sw = reinterpret_cast<const int*>(steps);
+  for (i64 t = t_begin + lb * 4 + wave; t < t_end; t += nb_x * 4) {
+    const Tile* tp = tiles + uniform64(t);
+    const i64 s0 = tp->step0;
+    const int ns = tp->nsteps;
+    f4 acc[4 * NG];
+#pragma unroll
+    for (int q = 0; q < 4 * NG; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+    if (ns > 0) {
+      int cur[8], nxt[8];
+      {
+        const int* src = sw + (s0 * 16) + 8 * lane;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) cur[e] = src[e];
+      }
+      s4 av[4], bv[NG];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
+        av[i] = *reinterpret_cast<const s4*>(A + (i64)max(rec_field(cur, 0, i), 0) * 16 + a_off);
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (mask >> (4 * i + j) & 1u) acc[4 * i + j] = __builtin_amdgcn_mfma_f32_4x4x1f32(av[i], bv[j], acc[4 * i + j], 0, 0, 0);
-    }
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const i32 cs = tp->cstrip[q];
-      if (cs < 0) continue;
-      f4 v = acc[q];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        v[e] += __shfl_xor(v[e], 4);
-        v[e] += __shfl_xor(v[e], 8);
+      for (int q = 0; q < NG; ++q) {
+        const int b0 = rec_field(cur, 0, 4 + 4 * q), b1 = rec_field(cur, 0, 5 + 4 * q);
+        const int b2 = rec_field(cur, 0, 6 + 4 * q), b3 = rec_field(cur, 0, 7 + 4 * q);
+        const int bl = g == 0 ? b0 : g == 1 ? b1 : g == 2 ? b2 : b3;
+        // one instruction covers 4 column quads: an absent strip must be zeros
+        const s4 z = {0, 0, 0, 0};
+        const s4 ld = *reinterpret_cast<const s4*>(B + (i64)max(bl, 0) * 64 + b_off);
+        bv[q] = bl >= 0 ? ld : z;
       }
-      const float r = kk == 0 ? v[0] : kk == 1 ? v[1] : kk == 2 ? v[2] : v[3];
-      const bool keep = (cmask[cs] >> t4) & 1;
-      const i64 idx = (i64)cs * 64 + lane;
-      float o = keep ? alpha * r : 0.f;
-      if (beta != 0.f) o += beta * C[idx];
-      C[idx] = o;
+      uint32_t mask = (uint32_t)rec_field(cur, 0, 4 + TJ);
+      const int nbatch = (ns + RB - 1) / RB;
+      for (int b = 0; b < nbatch; ++b) {
+        {
+          const int* src = sw + (s0 + (i64)RB * (b + 1)) * 16 + 8 * lane;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) nxt[e] = src[e];
+        }
+        const int rend = (ns - RB * b) < RB ? (ns - RB * b) : RB;
+        for (int r = 0; r < rend; ++r) {
+          int ra[4], rbl[NG];
+          uint32_t nmask;
+          if (r + 1 < RB) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ra[i] = rec_field(cur, r + 1, i);
+#pragma unroll
+            for (int q = 0; q < NG; ++q) {
+              const int b0 = rec_field(cur, r + 1, 4 + 4 * q), b1 = rec_field(cur, r + 1, 5 + 4 * q);
+              const int b2 = rec_field(cur, r + 1, 6 + 4 * q), b3 = rec_field(cur, r + 1, 7 + 4 * q);
+              rbl[q] = g == 0 ? b0 : g == 1 ? b1 : g == 2 ? b2 : b3;
+            }
+            nmask = (uint32_t)rec_field(cur, r + 1, 4 + TJ);
+          } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ra[i] = rec_field(nxt, 0, i);
+#pragma unroll
+            for (int q = 0; q < NG; ++q) {
+              const int b0 = rec_field(nxt, 0, 4 + 4 * q), b1 = rec_field(nxt, 0, 5 + 4 * q);
+              const int b2 = rec_field(nxt, 0, 6 + 4 * q), b3 = rec_field(nxt, 0, 7 + 4 * q);
+              rbl[q] = g == 0 ? b0 : g == 1 ? b1 : g == 2 ? b2 : b3;
+            }
+            nmask = (uint32_t)rec_field(nxt, 0, 4 + TJ);
+          }
+          if (RB * b + r + 1 >= ns) nmask = 0u;
+          s4 nav[4], nbv[NG];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) nav[i] = *reinterpret_cast<const s4*>(A + (i64)max(ra[i], 0) * 16 + a_off);
+#pragma unroll
+          for (int q = 0; q < NG; ++q) {
+            const s4 z = {0, 0, 0, 0};
+            const s4 ld = *reinterpret_cast<const s4*>(B + (i64)max(rbl[q], 0) * 64 + b_off);
+            nbv[q] = rbl[q] >= 0 ? ld : z;
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int q = 0; q < NG; ++q)
+              if ((mask >> (TJ * i + 4 * q)) & 15u)
+                acc[NG * i + q] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(av[i], bv[q], acc[NG * i + q], 0, 0, 0);
+          mask = nmask;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) av[i] = nav[i];
+#pragma unroll
+          for (int q = 0; q < NG; ++q) bv[q] = nbv[q];
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) cur[e] = nxt[e];
+      }
     }
-    (void)x;
+    // lane 4(4g + tb) + x holds D[r][x] (r = 0..3) of output strip (i, 4q + g), block tb
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int q = 0; q < NG; ++q) {
+        const i32 c0 = tp->cstrip[TJ * i + 4 * q], c1 = tp->cstrip[TJ * i + 4 * q + 1];
+        const i32 c2 = tp->cstrip[TJ * i + 4 * q + 2], c3 = tp->cstrip[TJ * i + 4 * q + 3];
+        const i32 cs = g == 0 ? c0 : g == 1 ? c1 : g == 2 ? c2 : c3;
+        if (cs < 0) continue;
+        const bool keep = (cmask[cs] >> tb) & 1;
+        const f4 v = acc[NG * i + q];
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const i64 idx = (i64)cs * 64 + tb * 16 + rr * 4 + x;
+          float o = keep ? alpha * v[rr] : 0.f;
+          if (beta != 0.f) o += beta * C[idx];
+          C[idx] = o;
+        }
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// plan steps (symbolic pass, on the GPU): one wavefront per tile; lane
+// (entry el, column jq) evaluates one inner entry against one output column
+// quad; the slot bits of an entry are OR-ed over its TJ lanes, active entries
+// become steps in inner-list order.  Count pass: steps per tile and the useful
+// work (integer atomics, so the totals are exact and order independent).  Fill
+// pass: writes the step records from the tile's first step.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_plan_steps(const Tile* __restrict__ tiles, i64 ntiles,
+                                                    const KEnt* __restrict__ kent, const i64* __restrict__ kbeg,
+                                                    PlanView v, int fill, i32* __restrict__ counts,
+                                                    Step* __restrict__ steps,
+                                                    unsigned long long* __restrict__ work) {
+  constexpr int EPI = 64 / TJ;   // inner entries per iteration
+  const int lane = threadIdx.x & 63;
+  const i64 wave0 = (i64)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const i64 nw = (i64)gridDim.x * 4;
+  const int jq = lane % TJ, el = lane / TJ;
+  for (i64 t = wave0; t < ntiles; t += nw) {
+    const Tile tl = tiles[t];
+    const i64 ck = tile_column_key(v, tl, jq);
+    const i64 kb = kbeg[tl.row_quad], ke = kbeg[tl.row_quad + 1];
+    i64 pos = tl.step0;
+    int cnt = 0;
+    uint64_t fl = 0, tr = 0;
+    for (i64 e0 = kb; e0 < ke; e0 += EPI) {
+      const i64 e = e0 + el;
+      i32 b = -1;
+      uint32_t bits = 0;
+      KEnt ent;
+      if (e < ke) {
+        ent = kent[e];
+        slot_work(v, tl, ent, jq, ck, &b, &bits, &fl, &tr);
+      }
+#pragma unroll
+      for (int o = 1; o < TJ; o <<= 1) bits |= (uint32_t)__shfl_xor((int)bits, o);
+      const bool active = bits != 0u;
+      const unsigned long long vote = __ballot(active && jq == 0);
+      if (fill && active) {
+        const int before = __popcll(vote & ((1ull << (el * TJ)) - 1ull));
+        int* sp = reinterpret_cast<int*>(steps + pos + before);
+        sp[4 + jq] = b;
+        if (jq == 0) {
+#pragma unroll
+          for (int ii = 0; ii < 4; ++ii) sp[ii] = ent.a[ii];
+          sp[4 + TJ] = (int)bits;
+#pragma unroll
+          for (int z = 5 + TJ; z < 16; ++z) sp[z] = 0;
+        }
+      }
+      const int nv = __popcll(vote);
+      pos += nv;
+      cnt += nv;
+    }
+    if (!fill) {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        fl += (uint64_t)__shfl_xor((long long)fl, o);
+        tr += (uint64_t)__shfl_xor((long long)tr, o);
+      }
+      if (lane == 0) {
+        counts[t] = cnt;
+        atomicAdd(work, (unsigned long long)fl);
+        atomicAdd(work + 1, (unsigned long long)tr);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Residual mode.  Each operand is split into its on-site part D (atom blocks
+// (a, a, 0); with pseudo-atoms, every pair of pseudo-atoms of one atom) and
+// the rest R: AB = R_A R_B + D_A B + A D_B - D_A D_B.  R_A R_B runs on the FP32
+// product kernel; the other three terms are block-diagonal scalings done here
+// in FP64, one thread per output block, finding the blocks it needs by binary
+// search in the strip lists.
+// ---------------------------------------------------------------------------
+struct PatDev {
+  const i64* sptr;
+  const i32* squad;
+  const i32* simg;
+  const uint8_t* smask;
+};
+
+// value offset of block (row, col, img) of a pattern, -1 when outside it
+__device__ __forceinline__ i64 block_off(const PatDev& p, i32 row, i32 col, i32 img) {
+  const i64 key = skey(col >> 2, img);
+  i64 lo = p.sptr[row], hi = p.sptr[row + 1];
+  while (lo < hi) {
+    const i64 mid = (lo + hi) >> 1;
+    if (skey(p.squad[mid], p.simg[mid]) < key) lo = mid + 1; else hi = mid;
+  }
+  if (lo < p.sptr[row + 1] && skey(p.squad[lo], p.simg[lo]) == key && ((p.smask[lo] >> (col & 3)) & 1))
+    return lo * 64 + (col & 3) * 16;
+  return -1;
+}
+
+// FP64 strips -> FP32 copy with the on-site blocks set to zero
+__global__ void k_offsite_f32(const double* __restrict__ in, float* __restrict__ out, const i32* __restrict__ srow,
+                              const i32* __restrict__ squad, const i32* __restrict__ simg,
+                              const i32* __restrict__ patom, i64 nstrips) {
+  for (i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x; g < nstrips * 64; g += (i64)gridDim.x * blockDim.x) {
+    const i64 st = g >> 6;
+    const int t = (int)((g >> 4) & 3);
+    const i32 p = srow[st], q = 4 * squad[st] + t;
+    const bool onsite = simg[st] == IMG0 && patom[p] >= 0 && patom[p] == patom[q];
+    out[g] = onsite ? 0.f : (float)in[g];
+  }
+}
+
+template <bool TA>
+__global__ void k_rc_correct(PatDev A, PatDev B, PatDev C, const i32* __restrict__ srow,
+                             const double* __restrict__ A64, const double* __restrict__ B64,
+                             const float* __restrict__ RR, double* __restrict__ C64, const i32* __restrict__ patom,
+                             const i32* __restrict__ pbase, const i32* __restrict__ npseudo, i64 ncstrips,
+                             double alpha, double beta) {
+  // op(A)_{p,(x,m)}: A's block (p, x, m), or the transpose of A's block (x, p, -m)
+  auto opa = [&](i32 p, i32 x, i32 m) -> i64 { return TA ? block_off(A, x, p, img_neg(m)) : block_off(A, p, x, m); };
+  for (i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x; g < ncstrips * 4; g += (i64)gridDim.x * blockDim.x) {
+    const i64 st = g >> 2;
+    const int t = (int)(g & 3);
+    const i64 base = st * 64 + t * 16;
+    double acc[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[e] = 0.0;
+    const bool in = (C.smask[st] >> t) & 1;
+    const i32 p = srow[st], q = 4 * C.squad[st] + t, n = C.simg[st];
+    auto add = [&](i64 a, i64 b, double sgn) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          double v = 0.0;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) v += (TA ? A64[a + k * 4 + r] : A64[a + r * 4 + k]) * B64[b + k * 4 + c];
+          acc[r * 4 + c] += sgn * v;
+        }
+    };
+    if (in) {
+      const i32 ap = patom[p], aq = patom[q];
+      // D_A B: the on-site blocks of row p times B's blocks (p', q, n)
+      for (i32 pp = pbase[ap]; pp < pbase[ap] + npseudo[ap]; ++pp) {
+        const i64 a = opa(p, pp, IMG0), b = block_off(B, pp, q, n);
+        if (a >= 0 && b >= 0) add(a, b, 1.0);
+      }
+      // A D_B: op(A)'s blocks (p, q', n) times the on-site blocks of column q
+      for (i32 qq = pbase[aq]; qq < pbase[aq] + npseudo[aq]; ++qq) {
+        const i64 a = opa(p, qq, n), b = block_off(B, qq, q, IMG0);
+        if (a >= 0 && b >= 0) add(a, b, 1.0);
+      }
+      // - D_A D_B (counted in both terms above)
+      if (ap == aq && n == IMG0)
+        for (i32 pp = pbase[ap]; pp < pbase[ap] + npseudo[ap]; ++pp) {
+          const i64 a = opa(p, pp, IMG0), b = block_off(B, pp, q, IMG0);
+          if (a >= 0 && b >= 0) add(a, b, -1.0);
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      double o = in ? alpha * ((double)RR[base + e] + acc[e]) : 0.0;
+      if (beta != 0.0) o += beta * C64[base + e];
+      C64[base + e] = o;
+    }
   }
 }
 
@@ -297,6 +818,7 @@ template void fill<float>(float*, i64, float, hipStream_t);
 
 template <class T>
 void user_to_strip(const lsdm_pattern* p, const double* user, T* strip, double scale, hipStream_t st) {
+  ensure_maps(const_cast<lsdm_pattern*>(p));
   if (p->n_sub == 0) return;
   hipLaunchKernelGGL(k_user_to_strip<T>, dim3(grid_for(p->n_sub * 16)), dim3(256), 0, st, user, strip,
                      p->d_sub_user.as<i64>(), p->d_sub_strip.as<i64>(), p->d_sub_shape.as<i32>(), p->n_sub, scale);
@@ -306,6 +828,7 @@ template void user_to_strip<float>(const lsdm_pattern*, const double*, float*, d
 
 template <class T>
 void strip_to_user(const lsdm_pattern* p, const T* strip, double* user, hipStream_t st) {
+  ensure_maps(const_cast<lsdm_pattern*>(p));
   if (p->n_sub == 0) return;
   hipLaunchKernelGGL(k_strip_to_user<T>, dim3(grid_for(p->n_sub * 16)), dim3(256), 0, st, strip, user,
                      p->d_sub_user.as<i64>(), p->d_sub_strip.as<i64>(), p->d_sub_shape.as<i32>(), p->n_sub);
@@ -315,6 +838,7 @@ template void strip_to_user<float>(const lsdm_pattern*, const float*, double*, h
 
 template <class T>
 void transpose_strips(const lsdm_pattern* p, const T* in, T* out, hipStream_t st) {
+  ensure_maps(const_cast<lsdm_pattern*>(p));
   if (p->n_strips == 0) return;
   hipLaunchKernelGGL(k_transpose_strips<T>, dim3(grid_for(p->n_strips * 64)), dim3(256), 0, st, in, out,
                      p->d_mirror.as<i64>(), p->n_strips);
@@ -322,41 +846,93 @@ void transpose_strips(const lsdm_pattern* p, const T* in, T* out, hipStream_t st
 template void transpose_strips<double>(const lsdm_pattern*, const double*, double*, hipStream_t);
 template void transpose_strips<float>(const lsdm_pattern*, const float*, float*, hipStream_t);
 
+// The product kernel deals tiles to the 8 XCDs in contiguous chunks and needs
+// at least one workgroup per XCD: the grid is a multiple of 8, at least 8.
 unsigned product_grid(i64 ntiles) {
   i64 blocks = (ntiles + 3) / 4;
   if (blocks > 16384) blocks = 16384;
-  if (blocks < 1) blocks = 1;
+  blocks = (blocks + 7) / 8 * 8;
+  if (blocks < 8) blocks = 8;
   return (unsigned)blocks;
 }
 
-template <>
-void product<double>(const lsdm_plan* pl, const double* A, const double* B, double* C, double alpha, double beta,
-                     hipStream_t st) {
+// which product kernel runs: the 4x4-block MFMA form (k_prod) or the dense
+// 16x16x4 form (k_prod16) on the same plans
+static bool dense_product_kernel() { return false; }
+
+template <class T>
+void product(const lsdm_plan* pl, const T* A, const T* B, T* C, double alpha, double beta, hipStream_t st) {
   if (pl->n_tiles == 0) return;
-  const Tile* T = pl->d_tiles.as<Tile>();
+  const Tile* Tl = pl->d_tiles.as<Tile>();
   const Step* S = pl->d_steps.as<Step>();
   const uint8_t* cm = pl->C->d_smask.as<uint8_t>();
+  const dim3 g(product_grid(pl->n_tiles)), b(256);
+  if (dense_product_kernel()) {
+    if (pl->transA)
+      hipLaunchKernelGGL((k_prod16<T, true>), g, b, 0, st, Tl, pl->n_tiles, S, A, B, C, cm, (T)alpha, (T)beta);
+    else
+      hipLaunchKernelGGL((k_prod16<T, false>), g, b, 0, st, Tl, pl->n_tiles, S, A, B, C, cm, (T)alpha, (T)beta);
+    return;
+  }
   if (pl->transA)
-    hipLaunchKernelGGL(k_prod_f64<true>, dim3(product_grid(pl->n_tiles)), dim3(256), 0, st, T, pl->n_tiles, S, A, B, C, cm,
-                       alpha, beta);
+    hipLaunchKernelGGL((k_prod<T, true>), g, b, 0, st, Tl, pl->n_tiles, S, A, B, C, cm, (T)alpha, (T)beta);
   else
-    hipLaunchKernelGGL(k_prod_f64<false>, dim3(product_grid(pl->n_tiles)), dim3(256), 0, st, T, pl->n_tiles, S, A, B, C,
-                       cm, alpha, beta);
+    hipLaunchKernelGGL((k_prod<T, false>), g, b, 0, st, Tl, pl->n_tiles, S, A, B, C, cm, (T)alpha, (T)beta);
+}
+template void product<double>(const lsdm_plan*, const double*, const double*, double*, double, double, hipStream_t);
+template void product<float>(const lsdm_plan*, const float*, const float*, float*, double, double, hipStream_t);
+
+void plan_steps(const Tile* tiles, i64 ntiles, const KEnt* kent, const i64* kbeg, const PlanView& v, int fill,
+                i32* counts, Step* steps, unsigned long long* work) {
+  if (ntiles == 0) return;
+  i64 blocks = (ntiles + 3) / 4;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_plan_steps, dim3((unsigned)blocks), dim3(256), 0, 0, tiles, ntiles, kent, kbeg, v, fill, counts,
+                     steps, work);
 }
 
-template <>
-void product<float>(const lsdm_plan* pl, const float* A, const float* B, float* C, double alpha, double beta,
-                    hipStream_t st) {
+static PatDev patdev(const lsdm_pattern* p) {
+  return PatDev{p->d_sptr.as<i64>(), p->d_squad.as<i32>(), p->d_simg.as<i32>(), p->d_smask.as<uint8_t>()};
+}
+
+void offsite_f32(const lsdm_pattern* p, const double* in, float* out, hipStream_t st) {
+  if (p->n_strips == 0) return;
+  hipLaunchKernelGGL(k_offsite_f32, dim3(grid_for(p->n_strips * 64)), dim3(256), 0, st, in, out, p->d_srow.as<i32>(),
+                     p->d_squad.as<i32>(), p->d_simg.as<i32>(), p->sys->d_patom.as<i32>(), p->n_strips);
+}
+
+void rc_correct(const lsdm_plan* pl, const double* A64, const double* B64, const float* RR, double* C64, double alpha,
+                double beta, hipStream_t st) {
+  const lsdm_pattern* C = pl->C;
+  if (C->n_strips == 0) return;
+  const lsdm_system* s = C->sys;
+  const dim3 g(grid_for(C->n_strips * 4)), b(256);
+  if (pl->transA)
+    hipLaunchKernelGGL((k_rc_correct<true>), g, b, 0, st, patdev(pl->A), patdev(pl->B), patdev(C), C->d_srow.as<i32>(),
+                       A64, B64, RR, C64, s->d_patom.as<i32>(), s->d_pbase.as<i32>(), s->d_npseudo.as<i32>(),
+                       C->n_strips, alpha, beta);
+  else
+    hipLaunchKernelGGL((k_rc_correct<false>), g, b, 0, st, patdev(pl->A), patdev(pl->B), patdev(C), C->d_srow.as<i32>(),
+                       A64, B64, RR, C64, s->d_patom.as<i32>(), s->d_pbase.as<i32>(), s->d_npseudo.as<i32>(),
+                       C->n_strips, alpha, beta);
+}
+
+void to_bf16(const float* in, unsigned short* outR, unsigned short* outC, i64 n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(n)), dim3(256), 0, st, in, outR, outC, n);
+}
+
+void product_bf16(const lsdm_plan* pl, const unsigned short* A, const unsigned short* B, float* C, double alpha,
+                  double beta, hipStream_t st) {
   if (pl->n_tiles == 0) return;
-  const Tile* T = pl->d_tiles.as<Tile>();
+  const Tile* Tl = pl->d_tiles.as<Tile>();
   const Step* S = pl->d_steps.as<Step>();
   const uint8_t* cm = pl->C->d_smask.as<uint8_t>();
+  const dim3 g(product_grid(pl->n_tiles)), b(256);
   if (pl->transA)
-    hipLaunchKernelGGL(k_prod_f32<true>, dim3(product_grid(pl->n_tiles)), dim3(256), 0, st, T, pl->n_tiles, S, A, B, C, cm,
-                       (float)alpha, (float)beta);
+    hipLaunchKernelGGL((k_prod_bf16<true>), g, b, 0, st, Tl, pl->n_tiles, S, A, B, C, cm, (float)alpha, (float)beta);
   else
-    hipLaunchKernelGGL(k_prod_f32<false>, dim3(product_grid(pl->n_tiles)), dim3(256), 0, st, T, pl->n_tiles, S, A, B, C,
-                       cm, (float)alpha, (float)beta);
+    hipLaunchKernelGGL((k_prod_bf16<false>), g, b, 0, st, Tl, pl->n_tiles, S, A, B, C, cm, (float)alpha, (float)beta);
 }
 
 template <class T>

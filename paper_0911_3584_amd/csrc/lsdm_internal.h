@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -84,9 +85,13 @@ struct lsdm_system {
   std::vector<lsdm::i32> npseudo;   // user atom -> number of pseudo-atoms
   std::vector<lsdm::i32> patom;     // pseudo-atom -> user atom
   std::vector<lsdm::i32> prows;     // pseudo-atom -> real rows (1..4)
+  std::vector<uint8_t> first;       // pseudo-atom -> 1 if first of its atom
   lsdm::i32 n_pseudo = 0;           // padded to a multiple of 4
   lsdm::i32 n_quads = 0;
   lsdm::DevBuf d_prows;             // i32[n_pseudo]
+  lsdm::DevBuf d_first;             // u8[n_pseudo]
+  lsdm::DevBuf d_patom;             // i32[n_pseudo], -1 for padding
+  lsdm::DevBuf d_pbase, d_npseudo;  // i32[n_atoms] (user atom -> first pseudo-atom, count)
 };
 
 struct lsdm_pattern {
@@ -106,39 +111,46 @@ struct lsdm_pattern {
   lsdm::i64 n_strips = 0;
   // device copies
   lsdm::DevBuf d_sptr, d_squad, d_simg, d_smask;
+  lsdm::DevBuf d_srow;              // i32 per strip: its row (pseudo-atom)
   // block layout <-> strip layout map: one entry per 4x4 sub-block of every
   // user block: user value offset of the sub-block's (0,0) element, its
   // strip-layout offset, and its real extent (rows, cols, user row stride)
   lsdm::i64 n_sub = 0;
   lsdm::DevBuf d_sub_user, d_sub_strip, d_sub_shape;   // i64, i64, i32 (rows | cols<<8 | stride<<16)
-  // strip-layout index of every on-site (i, i, 0) sub-block, for the
-  // block-diagonal terms of the residual mode
-  lsdm::DevBuf d_diag_strip;        // i64 per pseudo-atom: offset of block (p, p, 0), -1 if none
   // mirror map for transposes in strip layout: for strip s of row p, the
   // strip index of (q, quad(p), -n) for each of its 4 blocks q
   lsdm::DevBuf d_mirror;            // i64[4 * n_strips], -1 when absent
+  bool maps_ready = false;          // the three maps above are built on first use
+  std::mutex maps_mutex;
 };
 
 namespace lsdm {
 
-// One output tile of a product: a quad of 4 output rows x up to 4 column quads.
+// Tile width in column quads: one wavefront accumulates 4 output rows x TJ
+// column quads (4 * TJ slots of 4 blocks each).
+constexpr int TJ = 8;
+
+// One output tile of a product: a quad of 4 output rows x up to TJ column quads.
 struct Tile {
   i32 row_quad;
   i32 nsteps;
   i64 step0;
-  i32 cstrip[16];   // output strip of slot (i, jq) = [4*i + jq], -1 if absent
+  i32 cstrip[4 * TJ];   // output strip of slot (i, jq) = [TJ*i + jq], -1 if absent
 };
 
-// One step of a tile: a k pseudo-atom (with image) and its operands.
+// One step of a tile: a k pseudo-atom (with image) and its operands.  64 bytes,
+// read with one scalar load.
 //   a[i]: strip-layout offset / 16 of the 4x4 block A_{i,k} (or of X_{k,i} for a
 //         transposed A), -1 if absent
 //   b[jq]: strip index of B's strip (k, quad jq), -1 if absent
-//   mask: bit 4*i + jq set when slot (i, jq) has at least one useful triple
-struct Step {
+//   mask: bit TJ*i + jq set when slot (i, jq) has at least one useful triple
+struct alignas(64) Step {
   i32 a[4];
-  i32 b[4];
+  i32 b[TJ];
   uint32_t mask;
+  i32 pad[3];
 };
+static_assert(sizeof(Step) == 64, "step record is one 64-byte scalar load");
 
 }  // namespace lsdm
 
@@ -166,6 +178,14 @@ struct lsdm_lnv {
   lsdm::DevBuf wE;                  // partial sums for the energy
   // map from H's strips to M's strips (K assembly and 6H into Mbar)
   lsdm::DevBuf d_h2m;               // i64 per H strip: M strip index
+  // bf16 operand copies (allocated on first BF16 use): R = row-major blocks,
+  // C = block-transposed; L_R L_C S_C H_R H_C X_R X_C M_C Mb_R Mb_C Xb_R
+  lsdm::DevBuf b16[11];
+  bool b16_ready = false;
+  // residual mode: fp32 copies of the off-site parts (L S H X M Mb Xb) and the
+  // fp32 product of the off-site parts
+  lsdm::DevBuf r32[7], rr32;
+  bool rc_ready = false;
   // optional kernel timing: event pairs around product launches
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;

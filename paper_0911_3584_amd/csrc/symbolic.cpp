@@ -16,9 +16,12 @@
 #include <cstring>
 #include <numeric>
 #include <thread>
+#include <mutex>
 #include <unordered_map>
 
+#include "kernels.h"
 #include "lsdm_internal.h"
+#include "plan_common.h"
 
 namespace lsdm {
 
@@ -120,7 +123,13 @@ void build_system(lsdm_system* s) {
   }
   s->n_pseudo = (i32)s->patom.size();
   s->n_quads = s->n_pseudo / 4;
+  s->first.assign(s->n_pseudo, 0);
+  for (i32 q = 0; q < s->n_pseudo; ++q) s->first[q] = (s->patom[q] >= 0 && s->pbase[s->patom[q]] == q) ? 1 : 0;
   s->d_prows.upload(s->prows.data(), sizeof(i32) * s->prows.size());
+  s->d_first.upload(s->first.data(), s->first.size());
+  s->d_patom.upload(s->patom.data(), sizeof(i32) * s->patom.size());
+  s->d_pbase.upload(s->pbase.data(), sizeof(i32) * s->pbase.size());
+  s->d_npseudo.upload(s->npseudo.data(), sizeof(i32) * s->npseudo.size());
 }
 
 // ---------------------------------------------------------------------------
@@ -304,6 +313,26 @@ void build_strips(lsdm_pattern* p) {
   });
   rows.clear();
   rows.shrink_to_fit();
+  {
+    std::vector<i32> srow(p->n_strips);
+    for (i32 q = 0; q < np; ++q)
+      for (i64 st = p->sptr[q]; st < p->sptr[q + 1]; ++st) srow[st] = q;
+    p->d_srow.upload(srow.data(), sizeof(i32) * srow.size());
+  }
+  p->d_sptr.upload(p->sptr.data(), sizeof(i64) * p->sptr.size());
+  p->d_squad.upload(p->squad.data(), sizeof(i32) * p->squad.size());
+  p->d_simg.upload(p->simg.data(), sizeof(i32) * p->simg.size());
+  p->d_smask.upload(p->smask.data(), p->smask.size());
+}
+
+// Maps needed only by patterns that cross the boundary or are transposed:
+// block layout <-> strip layout (per 4x4 sub-block), on-site sub-blocks and
+// the mirror map.  Built on first use.
+void ensure_maps(lsdm_pattern* p) {
+  std::lock_guard<std::mutex> lk(p->maps_mutex);
+  if (p->maps_ready) return;
+  const lsdm_system* s = p->sys;
+  const i32 n = s->n_atoms, np = s->n_pseudo;
   // sub-block maps between the two layouts
   std::vector<i64> subcnt(n + 1, 0);
   for (i32 a = 0; a < n; ++a) {
@@ -333,14 +362,6 @@ void build_strips(lsdm_pattern* p) {
   p->d_sub_user.upload(su.data(), sizeof(i64) * su.size());
   p->d_sub_strip.upload(ss.data(), sizeof(i64) * ss.size());
   p->d_sub_shape.upload(sh.data(), sizeof(i32) * sh.size());
-  // on-site sub-blocks: every (p, p, 0) pair
-  std::vector<i64> diag(np, -1);
-  for (i32 q = 0; q < np; ++q) {
-    if (s->patom[q] < 0) continue;
-    i64 st = find_strip(p, q, skey(q >> 2, IMG0));
-    if (st >= 0 && (p->smask[st] >> (q & 3) & 1)) diag[q] = st * 64 + (q & 3) * 16;
-  }
-  p->d_diag_strip.upload(diag.data(), sizeof(i64) * diag.size());
   // mirror map: block t of strip s in row q is (q, 4Q+t, n); its mirror is
   // (4Q+t, q, -n), found in strip (4Q+t, quad(q), -n) at block q & 3
   std::vector<i64> mir(4 * (size_t)p->n_strips, -1);
@@ -354,15 +375,19 @@ void build_strips(lsdm_pattern* p) {
       }
   });
   p->d_mirror.upload(mir.data(), sizeof(i64) * mir.size());
-  p->d_sptr.upload(p->sptr.data(), sizeof(i64) * p->sptr.size());
-  p->d_squad.upload(p->squad.data(), sizeof(i32) * p->squad.size());
-  p->d_simg.upload(p->simg.data(), sizeof(i32) * p->simg.size());
-  p->d_smask.upload(p->smask.data(), p->smask.size());
+  p->maps_ready = true;
 }
 
 // ---------------------------------------------------------------------------
-// product plan: tiles (4 output rows x up to 4 output column quads) and steps
+// product plan: tiles (4 output rows x up to TJ output column quads) and steps
+//
+// Host: per row quad, the inner list (union over its 4 rows of A's blocks
+// (k, m), with each row's block) and the tiles (its output column quads in
+// groups of TJ).  Device: the steps of every tile (k_plan_steps), so the task
+// list, which is the bulk of a plan, never passes through host memory.
 // ---------------------------------------------------------------------------
+bool have_device();
+
 void build_plan(lsdm_plan* pl) {
   const lsdm_pattern* A = pl->A;
   const lsdm_pattern* B = pl->B;
@@ -370,42 +395,44 @@ void build_plan(lsdm_plan* pl) {
   const lsdm_system* s = C->sys;
   const i32 nq = s->n_quads;
   std::vector<std::vector<Tile>> tiles(nq);
-  std::vector<std::vector<Step>> steps(nq);
-  std::vector<i64> triples(nq, 0);
-  std::vector<double> flops(nq, 0.0);
+  std::vector<std::vector<KEnt>> kents(nq);
   const bool tA = pl->transA != 0;
   parallel_for(nq, [&](i64 I) {
-    // k-list: the union over the 4 rows of A's blocks (k, m) with the pointer of
-    // each row's block; for a transposed A the row pattern is A's own (range
-    // patterns are symmetric) and the block is the transpose of A_{k,(i,-m)}
-    std::vector<std::pair<i64, std::array<i32, 4>>> kl;
-    {
-      std::vector<std::pair<i64, std::pair<int, i32>>> raw;
-      for (int ii = 0; ii < 4; ++ii) {
-        i32 row = 4 * (i32)I + ii;
-        for (i64 st = A->sptr[row]; st < A->sptr[row + 1]; ++st)
-          for (int t = 0; t < 4; ++t) {
-            if (!(A->smask[st] >> t & 1)) continue;
-            i32 k = 4 * A->squad[st] + t;
-            i32 m = A->simg[st];
-            i64 blk;
-            if (!tA) {
-              blk = st * 4 + t;
-            } else {
-              i64 ms = find_strip(A, k, skey(row >> 2, img_neg(m)));
-              if (ms < 0) LSDM_THROW(LSDM_EPATTERN, "transposed operand pattern is not symmetric");
-              blk = ms * 4 + (row & 3);
-            }
-            raw.push_back({((i64)k << 24) | m, {ii, (i32)blk}});
+    // inner list: the union over the 4 rows of A's blocks (k, m); for a
+    // transposed A the row pattern is A's own (range patterns are symmetric)
+    // and the block is the transpose of A_{k,(i,-m)}
+    std::vector<std::pair<i64, std::pair<int, i32>>> raw;
+    for (int ii = 0; ii < 4; ++ii) {
+      i32 row = 4 * (i32)I + ii;
+      for (i64 st = A->sptr[row]; st < A->sptr[row + 1]; ++st)
+        for (int t = 0; t < 4; ++t) {
+          if (!(A->smask[st] >> t & 1)) continue;
+          i32 k = 4 * A->squad[st] + t;
+          i32 m = A->simg[st];
+          i64 blk;
+          if (!tA) {
+            blk = st * 4 + t;
+          } else {
+            i64 ms = find_strip(A, k, skey(row >> 2, img_neg(m)));
+            if (ms < 0) LSDM_THROW(LSDM_EPATTERN, "transposed operand pattern is not symmetric");
+            blk = ms * 4 + (row & 3);
           }
-      }
-      std::sort(raw.begin(), raw.end());
-      for (auto& e : raw) {
-        if (kl.empty() || kl.back().first != e.first) kl.push_back({e.first, {-1, -1, -1, -1}});
-        kl.back().second[e.second.first] = e.second.second;
-      }
+          raw.push_back({((i64)k << 24) | m, {ii, (i32)blk}});
+        }
     }
-    // output column quads of the 4 rows of C, grouped 4 per tile
+    std::sort(raw.begin(), raw.end());
+    auto& K = kents[I];
+    for (auto& e : raw) {
+      if (K.empty() || (((i64)K.back().k << 24) | K.back().m) != e.first) {
+        KEnt ke;
+        ke.k = (i32)(e.first >> 24);
+        ke.m = (i32)(e.first & 0xffffff);
+        for (int ii = 0; ii < 4; ++ii) ke.a[ii] = -1;
+        K.push_back(ke);
+      }
+      K.back().a[e.second.first] = e.second.second;
+    }
+    // output column quads of the 4 rows of C, grouped TJ per tile
     std::vector<i64> ckeys;
     for (int ii = 0; ii < 4; ++ii) {
       i32 row = 4 * (i32)I + ii;
@@ -413,101 +440,118 @@ void build_plan(lsdm_plan* pl) {
     }
     std::sort(ckeys.begin(), ckeys.end());
     ckeys.erase(std::unique(ckeys.begin(), ckeys.end()), ckeys.end());
-    const i64 nt = ((i64)ckeys.size() + 3) / 4;
+    const i64 nt = ((i64)ckeys.size() + TJ - 1) / TJ;
     std::vector<Tile> T(nt);
-    std::vector<uint8_t> cm(nt * 16, 0);
-    std::unordered_map<i64, i32> cpos;   // column key -> 4*tile + jq
-    cpos.reserve(ckeys.size() * 2);
-    for (size_t c = 0; c < ckeys.size(); ++c) cpos[ckeys[c]] = (i32)c;
     for (i64 t = 0; t < nt; ++t) {
       T[t].row_quad = (i32)I;
-      for (int q = 0; q < 16; ++q) T[t].cstrip[q] = -1;
+      T[t].nsteps = 0;
+      T[t].step0 = 0;
+      for (int q = 0; q < 4 * TJ; ++q) T[t].cstrip[q] = -1;
     }
     for (int ii = 0; ii < 4; ++ii) {
       i32 row = 4 * (i32)I + ii;
       for (i64 st = C->sptr[row]; st < C->sptr[row + 1]; ++st) {
-        i32 c = cpos[skey(C->squad[st], C->simg[st])];
-        T[c / 4].cstrip[4 * ii + (c & 3)] = (i32)st;
-        cm[(c / 4) * 16 + 4 * ii + (c & 3)] = C->smask[st];
+        const i64 c = std::lower_bound(ckeys.begin(), ckeys.end(), skey(C->squad[st], C->simg[st])) - ckeys.begin();
+        T[c / TJ].cstrip[TJ * ii + (c % TJ)] = (i32)st;
       }
-    }
-    // per tile and k: the B strips reaching its column quads
-    const size_t nk = kl.size();
-    std::vector<i32> bidx(nt * nk * 4, -1);
-    std::vector<uint8_t> bmask(nt * nk * 4, 0);
-    for (size_t kk = 0; kk < nk; ++kk) {
-      i32 k = (i32)(kl[kk].first >> 24);
-      i32 m = (i32)(kl[kk].first & 0xffffff);
-      for (i64 st = B->sptr[k]; st < B->sptr[k + 1]; ++st) {
-        auto it = cpos.find(skey(B->squad[st], img_add(m, B->simg[st])));
-        if (it == cpos.end()) continue;   // outside C's range for every row: truncated
-        i32 c = it->second;
-        size_t w = ((size_t)(c / 4) * nk + kk) * 4 + (c & 3);
-        bidx[w] = (i32)st;
-        bmask[w] = B->smask[st];
-      }
-    }
-    auto& S = steps[I];
-    for (i64 t = 0; t < nt; ++t) {
-      T[t].step0 = (i64)S.size();
-      for (size_t kk = 0; kk < nk; ++kk) {
-        Step st;
-        st.mask = 0;
-        i32 k = (i32)(kl[kk].first >> 24);
-        for (int ii = 0; ii < 4; ++ii) st.a[ii] = kl[kk].second[ii];
-        for (int jq = 0; jq < 4; ++jq) st.b[jq] = bidx[((size_t)t * nk + kk) * 4 + jq];
-        for (int ii = 0; ii < 4; ++ii) {
-          if (st.a[ii] < 0) continue;
-          for (int jq = 0; jq < 4; ++jq) {
-            if (st.b[jq] < 0) continue;
-            uint8_t u = bmask[((size_t)t * nk + kk) * 4 + jq] & cm[t * 16 + 4 * ii + jq];
-            if (!u) continue;
-            st.mask |= 1u << (4 * ii + jq);
-            const i32 ri = s->prows[4 * I + ii], rk = s->prows[k];
-            const i32 jbase = 4 * (i32)(ckeys[4 * t + jq] >> 24);
-            for (int b = 0; b < 4; ++b) {
-              if (!(u >> b & 1)) continue;
-              flops[I] += 2.0 * ri * rk * s->prows[jbase + b];
-              // count each atom triple once: the first pseudo-atom of every atom
-              const i32 pi = 4 * (i32)I + ii, pj = jbase + b;
-              if (pi == s->pbase[s->patom[pi]] && k == s->pbase[s->patom[k]] && pj == s->pbase[s->patom[pj]])
-                ++triples[I];
-            }
-          }
-        }
-        if (st.mask) S.push_back(st);
-      }
-      T[t].nsteps = (i32)((i64)S.size() - T[t].step0);
     }
     tiles[I] = std::move(T);
   }, 4);
-  // concatenate
-  i64 ntile = 0, nstep = 0;
-  for (i32 I = 0; I < nq; ++I) {
-    ntile += (i64)tiles[I].size();
-    nstep += (i64)steps[I].size();
-  }
+  // inner lists and tiles in one array each
+  std::vector<i64> kbeg(nq + 1, 0);
+  for (i32 I = 0; I < nq; ++I) kbeg[I + 1] = kbeg[I] + (i64)kents[I].size();
+  std::vector<KEnt> allK(kbeg[nq]);
+  parallel_for(nq, [&](i64 I) { std::copy(kents[I].begin(), kents[I].end(), allK.begin() + kbeg[I]); });
+  std::vector<std::vector<KEnt>>().swap(kents);
   std::vector<Tile> allT;
-  allT.reserve(ntile);
-  std::vector<Step> allS;
-  allS.reserve(nstep);
-  pl->n_triples = 0;
-  pl->flops = 0;
-  for (i32 I = 0; I < nq; ++I) {
-    i64 base = (i64)allS.size();
-    for (auto t : tiles[I]) {
-      t.step0 += base;
-      allT.push_back(t);
+  for (i32 I = 0; I < nq; ++I) allT.insert(allT.end(), tiles[I].begin(), tiles[I].end());
+  std::vector<std::vector<Tile>>().swap(tiles);
+  // Traversal order (a GEMM-style swizzle): super-rows of SUPER row quads, and
+  // inside a super-row by output column, so tiles that run together on one
+  // XCD share B strips (same columns, neighbouring rows) and A blocks (same
+  // rows) through its L2.
+  {
+    constexpr i32 SUPER = 8;
+    std::vector<std::pair<std::pair<i64, i64>, i64>> key(allT.size());
+    for (size_t t = 0; t < allT.size(); ++t) {
+      i32 c0 = -1;
+      for (int q = 0; q < 4 * TJ && c0 < 0; ++q)
+        if (allT[t].cstrip[q] >= 0) c0 = C->squad[allT[t].cstrip[q]];
+      key[t] = {{allT[t].row_quad / SUPER, c0}, (i64)t};
     }
-    allS.insert(allS.end(), steps[I].begin(), steps[I].end());
-    pl->n_triples += triples[I];
-    pl->flops += flops[I];
-    std::vector<Step>().swap(steps[I]);
+    std::sort(key.begin(), key.end());
+    std::vector<Tile> ord(allT.size());
+    for (size_t t = 0; t < allT.size(); ++t) ord[t] = allT[key[t].second];
+    allT.swap(ord);
   }
+  const i64 ntile = (i64)allT.size();
   pl->n_tiles = ntile;
-  pl->n_steps = nstep;
-  pl->d_tiles.upload(allT.data(), sizeof(Tile) * allT.size());
-  pl->d_steps.upload(allS.data(), sizeof(Step) * allS.size());
+  if (have_device()) {
+    DevBuf d_k, d_kb, d_cnt, d_work;
+    d_k.upload(allK.data(), sizeof(KEnt) * allK.size());
+    d_kb.upload(kbeg.data(), sizeof(i64) * kbeg.size());
+    pl->d_tiles.upload(allT.data(), sizeof(Tile) * allT.size());
+    d_cnt.alloc(sizeof(i32) * (ntile + 1));
+    d_work.alloc(16);
+    HIP_CHECK(hipMemset(d_work.p, 0, 16));
+    PlanView v{B->d_sptr.as<i64>(), B->d_squad.as<i32>(), B->d_simg.as<i32>(), B->d_smask.as<uint8_t>(),
+               C->d_squad.as<i32>(), C->d_simg.as<i32>(), C->d_smask.as<uint8_t>(), s->d_prows.as<i32>(),
+               s->d_first.as<uint8_t>()};
+    plan_steps(pl->d_tiles.as<Tile>(), ntile, d_k.as<KEnt>(), d_kb.as<i64>(), v, 0, d_cnt.as<i32>(), nullptr,
+               d_work.as<unsigned long long>());
+    HIP_CHECK(hipGetLastError());
+    std::vector<i32> cnt(ntile);
+    uint64_t work[2];
+    if (ntile) HIP_CHECK(hipMemcpy(cnt.data(), d_cnt.p, sizeof(i32) * ntile, hipMemcpyDeviceToHost));
+    HIP_CHECK(hipMemcpy(work, d_work.p, 16, hipMemcpyDeviceToHost));
+    i64 nstep = 0;
+    for (i64 t = 0; t < ntile; ++t) {
+      allT[t].step0 = nstep;
+      allT[t].nsteps = cnt[t];
+      nstep += cnt[t];
+    }
+    pl->n_steps = nstep;
+    pl->flops = (double)work[0];
+    pl->n_triples = (i64)work[1];
+    pl->d_tiles.upload(allT.data(), sizeof(Tile) * allT.size());
+    // the product kernel reads step records in batches of 32 and may read one
+    // batch past the last step: pad with zero records
+    pl->d_steps.alloc(sizeof(Step) * (nstep + 64));
+    HIP_CHECK(hipMemset(pl->d_steps.p, 0, sizeof(Step) * (nstep + 64)));
+    plan_steps(pl->d_tiles.as<Tile>(), ntile, d_k.as<KEnt>(), d_kb.as<i64>(), v, 1, nullptr, pl->d_steps.as<Step>(),
+               nullptr);
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipDeviceSynchronize());
+  } else {
+    // no device: the same step generation on the host (counts only are kept)
+    PlanView v{B->sptr.data(), B->squad.data(), B->simg.data(), B->smask.data(), C->squad.data(), C->simg.data(),
+               C->smask.data(), s->prows.data(), s->first.data()};
+    std::vector<uint64_t> fl(ntile, 0), tr(ntile, 0);
+    std::vector<i64> ns(ntile, 0);
+    parallel_for(ntile, [&](i64 t) {
+      const Tile& tl = allT[t];
+      i64 ck[TJ];
+      for (int jq = 0; jq < TJ; ++jq) ck[jq] = tile_column_key(v, tl, jq);
+      for (i64 e = kbeg[tl.row_quad]; e < kbeg[tl.row_quad + 1]; ++e) {
+        uint32_t all = 0;
+        for (int jq = 0; jq < TJ; ++jq) {
+          i32 b;
+          uint32_t bits;
+          slot_work(v, tl, allK[e], jq, ck[jq], &b, &bits, &fl[t], &tr[t]);
+          all |= bits;
+        }
+        if (all) ++ns[t];
+      }
+    }, 16);
+    pl->n_steps = 0;
+    pl->flops = 0;
+    pl->n_triples = 0;
+    for (i64 t = 0; t < ntile; ++t) {
+      pl->n_steps += ns[t];
+      pl->flops += (double)fl[t];
+      pl->n_triples += (i64)tr[t];
+    }
+  }
 }
 
 }  // namespace lsdm

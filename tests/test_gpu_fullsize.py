@@ -1,0 +1,196 @@
+"""GPU checks at the full workload sizes and in reduced precision.
+
+At full size the oracle computes sampled rows one by one through their
+dependency cones (K rows and dE/dL rows); the energy of a perfect crystal is
+checked through extensivity against the oracle's 64-atom cell; dE/dL is checked
+against exact Richardson differences of the GPU's own energy (E is a cubic
+polynomial of L).  Reduced-precision chains state their energy error per atom
+against FP64.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests._sides import gpu_values, rel, same_pattern
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_0911_3584_amd as lsdm  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def T(x):
+    return torch.from_numpy(np.ascontiguousarray(x, np.float64)).to(DEV)
+
+
+def setup(s, rS, rH, rL):
+    lnv = lsdm.LNV(lsdm.System.from_workload(s), rS, rH, rL)
+    v = {w: T(gpu_values(lnv.patterns[w], s, w, rS=rS)) for w in "LSH"}
+    return lnv, v
+
+
+def row_block(pattern_gpu, vec, i):
+    rp, col, img, off = pattern_gpu.export()
+    nfn = pattern_gpu.system.nfn
+    lo = off[rp[i]]
+    last = rp[i + 1] - 1
+    hi = off[last] + nfn[i] * nfn[col[last]]
+    return vec[lo:hi]
+
+
+def check_rows(lnv, s, v, rS, rH, rL, rows, grad_rows=None, K=None, G=None):
+    """K rows (and dE/dL rows) against the oracle's dependency cones."""
+    ec = oracle.energy_cone(s, rS, rH, rL, rows)
+    lrows = ec["L"] if grad_rows is None else np.union1d(ec["L"], oracle.gradient_cone(s, rS, rH, rL, grad_rows)["L"])
+    srows = ec["S"] if grad_rows is None else np.union1d(ec["S"], oracle.gradient_cone(s, rS, rH, rL, grad_rows)["S"])
+    hrows = np.union1d(ec["H"], rows) if grad_rows is None else np.union1d(
+        np.union1d(ec["H"], rows), oracle.gradient_cone(s, rS, rH, rL, grad_rows)["H"])
+    inp = oracle.make_inputs(s, rS, rH, rL, rows_L=lrows, rows_S=srows, rows_H=hrows)
+    ref = oracle.lnv_energy(inp["L"], inp["S"], inp["H"], rS, rH, rL, rows=rows)
+    Kh = K.cpu().numpy()
+    for i in rows:
+        got = row_block(lnv.patterns["H"], Kh, i)
+        assert rel(got, oracle.row_slice(ref["K"], i)) <= 1e-12, i
+    if grad_rows is not None:
+        Gr = oracle.lnv_gradient(inp["L"], inp["S"], inp["H"], rS, rH, rL, rows=grad_rows)
+        Gh = G.cpu().numpy()
+        for i in grad_rows:
+            assert rel(row_block(lnv.patterns["L"], Gh, i), oracle.row_slice(Gr, i)) <= 1e-12, i
+    return ref
+
+
+def fd_check(lnv, v, G, n_blocks=20, h=0.25, prec="fp64", seed=0, tol=1e-7):
+    """Richardson-extrapolated central differences of E along single stored L
+    blocks (exact for a cubic up to rounding) against <dE/dL, direction>."""
+    p = lnv.patterns["L"]
+    rp, col, img, off = p.export()
+    nfn = p.system.nfn
+    rows = np.repeat(np.arange(p.system.n), np.diff(rp))
+    blocks = workloads.fd_blocks(p.n_blocks, n_blocks, seed=seed)
+    dirs = workloads.fd_direction(p.n_values, seed=seed)
+    Lh = v["L"].clone()
+    g = G.cpu().numpy()
+    worst = 0.0
+    for b in blocks:
+        sz = int(nfn[rows[b]] * nfn[col[b]])
+        d = np.zeros(p.n_values)
+        d[off[b]:off[b] + sz] = dirs[off[b]:off[b] + sz]
+        dt = T(d)
+
+        def E(t):
+            Lh.copy_(v["L"]).add_(dt, alpha=t)
+            return lnv.energy(Lh, v["S"], v["H"], prec=prec).item()
+        d1 = (E(h) - E(-h)) / (2 * h)
+        d2 = (E(h / 2) - E(-h / 2)) / h
+        fd = (4 * d2 - d1) / 3
+        an = float(np.dot(g, d))
+        err = abs(fd - an) / max(1.0, abs(an))
+        worst = max(worst, err)
+        assert err <= tol, (int(b), fd, an)
+    return worst
+
+
+# ---------------------------------------------------------------------------
+# reduced precision on small chains
+# ---------------------------------------------------------------------------
+SMALL = {
+    "config1_si64": lambda: (workloads.config(1)["system"], 8.0, 12.0, 12.0),
+    "mixed_box_13_5": lambda: (workloads.random_box(300, 17.5, 240, 13, 5, seed=2), 6.0, 8.0, 8.0),
+}
+# chain error allowances, relative: about ten times the observed error of a
+# five-product chain whose inputs are rounded with unit roundoff u
+# (FP32 u = 2^-24, BF16 u = 2^-8); each single product is held to its a-priori
+# bound in test_gpu_parity.py
+CHAIN_TOL = {"fp32": (1e-5, 1e-4), "bf16": (3e-2, 1.5e-1), "fp32_rc": (1e-8, 1e-6)}
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp32_rc"])
+@pytest.mark.parametrize("name", list(SMALL))
+def test_lnv_reduced_precision(prec, name):
+    s, rS, rH, rL = SMALL[name]()
+    say(f"[reduced] {name} {prec}")
+    lnv, v = setup(s, rS, rH, rL)
+    inp = oracle.make_inputs(s, rS, rH, rL)
+    ref = oracle.lnv_energy(inp["L"], inp["S"], inp["H"], rS, rH, rL)
+    Gref = oracle.lnv_gradient(inp["L"], inp["S"], inp["H"], rS, rH, rL)
+    E, G = lnv.energy_grad(v["L"], v["S"], v["H"], prec=prec)
+    eE = abs(E.item() - ref["E"]) / abs(ref["E"])
+    eG = rel(G.cpu().numpy(), Gref.val)
+    say(f"    E rel err {eE:.3e} ({1e6 * abs(E.item() - ref['E']) / s.n:.4f} uHa/atom), dE/dL rel err {eG:.3e}")
+    assert eE <= CHAIN_TOL[prec][0] and eG <= CHAIN_TOL[prec][1]
+
+
+# ---------------------------------------------------------------------------
+# full sizes
+# ---------------------------------------------------------------------------
+def test_config3_jitter_fp64_rows_and_fd():
+    c = workloads.config(3)
+    s = c["system"]
+    rS, rH, rL = c["rS"], c["rH"], c["rL"]
+    say(f"[config3] {s.n} atoms, jittered, RL16: setup")
+    lnv, v = setup(s, rS, rH, rL)
+    E, K = lnv.energy(v["L"], v["S"], v["H"], want_K=True)
+    _, G = lnv.energy_grad(v["L"], v["S"], v["H"])
+    say("[config3] oracle rows")
+    rows = np.array([0, 6911, 13823])
+    check_rows(lnv, s, v, rS, rH, rL, rows, grad_rows=np.array([5000]), K=K, G=G)
+    # E equals the sum of the per-row contributions 2 <K_i, H_i> (FP64 on the host)
+    Hh = v["H"].cpu().numpy()
+    assert abs(float(np.sum(K.cpu().numpy() * Hh)) * 2 - E.item()) <= 1e-12 * abs(E.item())
+    say("[config3] finite differences on 20 L blocks")
+    worst = fd_check(lnv, v, G, n_blocks=20)
+    say(f"    worst FD relative deviation {worst:.2e}")
+
+
+def test_config4_extensive_energy_rows_and_modes():
+    c = workloads.config(4)
+    s = c["system"]
+    rS, rH, rL = c["rS"], c["rH"], c["rL"]
+    say(f"[config4] {s.n} atoms, RL16: setup")
+    lnv, v = setup(s, rS, rH, rL)
+    E, K = lnv.energy(v["L"], v["S"], v["H"], want_K=True)
+    _, G = lnv.energy_grad(v["L"], v["S"], v["H"])
+    # translation-class values make E extensive: the 64-atom cell fixes E/N
+    small = workloads.diamond(2)
+    inp = oracle.make_inputs(small, rS, rH, rL)
+    e_small = oracle.lnv_energy(inp["L"], inp["S"], inp["H"], rS, rH, rL)["E"] / small.n
+    assert abs(E.item() / s.n - e_small) <= 1e-12 * abs(e_small), (E.item() / s.n, e_small)
+    say("[config4] oracle rows")
+    check_rows(lnv, s, v, rS, rH, rL, np.array([0, 12345, 32767]), grad_rows=np.array([20000]), K=K, G=G)
+    for prec in ("fp32", "bf16", "fp32_rc"):
+        Em, Gm = lnv.energy_grad(v["L"], v["S"], v["H"], prec=prec)
+        eE = abs(Em.item() - E.item()) / abs(E.item())
+        eG = rel(Gm.cpu().numpy(), G.cpu().numpy())
+        say(f"    {prec}: E rel err {eE:.3e} = {1e6 * abs(Em.item() - E.item()) / s.n:.4f} uHa/atom; dE/dL rel {eG:.3e}")
+        assert eE <= CHAIN_TOL[prec][0] and eG <= CHAIN_TOL[prec][1]
+
+
+def test_config5_mixed_blocks_rows_and_fd():
+    c = workloads.config(5)
+    s = c["system"]
+    rS, rH, rL = c["rS"], c["rH"], c["rL"]
+    say(f"[config5] {s.n} atoms, 13/5 functions: setup")
+    lnv, v = setup(s, rS, rH, rL)
+    E, K = lnv.energy(v["L"], v["S"], v["H"], want_K=True)
+    _, G = lnv.energy_grad(v["L"], v["S"], v["H"])
+    say("[config5] oracle rows")
+    check_rows(lnv, s, v, rS, rH, rL, np.array([0, 4000, 7999]), K=K)
+    say("[config5] finite differences on 8 L blocks")
+    fd_check(lnv, v, G, n_blocks=8, seed=5)
+    Em, Gm = lnv.energy_grad(v["L"], v["S"], v["H"], prec="fp32")
+    eE = abs(Em.item() - E.item()) / abs(E.item())
+    say(f"    fp32: E rel err {eE:.3e} = {1e6 * abs(Em.item() - E.item()) / s.n:.4f} uHa/atom")
+    assert eE <= CHAIN_TOL["fp32"][0]

@@ -58,8 +58,18 @@ def _rand(p, seed):
     return np.random.default_rng(seed).normal(size=p.nval)
 
 
+def _offsite(p, v):
+    """Values with the on-site blocks (i, i, image 0) set to zero."""
+    v = v.copy()
+    bi, bj, bim = p.keys()
+    nfn = np.asarray(p.system.nfn, np.int64)
+    for b in np.where((bi == bj) & np.all(bim == 0, axis=1))[0]:
+        v[p.off[b]:p.off[b] + nfn[bi[b]] * nfn[bj[b]]] = 0.0
+    return v
+
+
 @pytest.mark.parametrize("case", PRODUCT_CASES, ids=[c[0] for c in PRODUCT_CASES])
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16", "fp32_rc"])
 def test_product_parity(case, prec):
     name, mk, (rA, rB, rC), tA, tB, alpha, beta = case
     say(f"[product] {name} prec={prec} ranges={rA},{rB},{rC} tA={tA} tB={tB}")
@@ -77,12 +87,21 @@ def test_product_parity(case, prec):
     if prec == "fp64":
         assert rel(got, ref) <= TOL64, rel(got, ref)
     else:
-        # |fl(sum ab) - sum ab| <= gamma_n sum |a||b| with inputs rounded to fp32
+        # a-priori bound (Higham, Accuracy and Stability of Numerical Algorithms,
+        # sec. 3.1): inputs rounded with unit roundoff ui (relative error of a
+        # product of two rounded inputs <= 2 ui + ui^2), then n-term FP32
+        # accumulation, |fl(sum ab) - sum ab| <= (2 ui + ui^2 + gamma_n) sum |a||b|
+        if prec == "fp32_rc":
+            # only the off-site parts are multiplied in FP32; the on-site (atom
+            # diagonal, image 0) terms are exact FP64 scalings
+            a, b = _offsite(oA, a), _offsite(oB, b)
         absref = oracle.multiply_op(oracle.Matrix(oA, np.abs(a)), tA, oracle.Matrix(oB, np.abs(b)), tB, oC).val
         n = 4 * int(np.diff(oA.row_ptr).max()) * 4 + 8   # summands per output element, generously
         u = 2.0 ** -24
-        bound = abs(alpha) * (n + 2) * u / (1 - (n + 2) * u) * absref + 4 * u * np.abs(beta * c0) + 1e-30
-        assert np.all(np.abs(got - ref) <= bound + 4 * u * np.abs(ref))
+        ui = 2.0 ** -8 if prec == "bf16" else u
+        gam = (n + 2) * u / (1 - (n + 2) * u)
+        bound = abs(alpha) * (2 * ui + ui * ui + gam) * absref + 4 * u * np.abs(beta * c0) + 4 * u * np.abs(ref) + 1e-30
+        assert np.all(np.abs(got - ref) <= bound), np.max(np.abs(got - ref) / (bound + 1e-300))
 
 
 def test_product_adjoint_and_dot():
