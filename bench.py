@@ -135,20 +135,18 @@ def summarize_pmc(fetch_dir, write_dir, prec, out):
                 continue
             per.setdefault(int(r["Dispatch_Id"]), [r["Kernel_Name"], 0.0])[1] += float(r["Counter_Value"])
         res[name] = per
-    calib = None
-    for did, (kn, v) in sorted(res["FETCH_SIZE"].items()):
-        if "copy" in kn.lower() or "elementwise" in kn.lower():
-            if v > 900 * 1024:   # the 1 GiB calibration copy
-                calib = did
-                break
-    if calib is None:
-        raise SystemExit("calibration copy dispatch not found")
+    # the calibration copy: the copy dispatch that writes the most (its write
+    # count is the copy size; the fetch counter may read a fraction of it)
+    copies = [(v, did) for did, (kn, v) in res["WRITE_SIZE"].items() if "copy" in kn.lower()]
+    if not copies or max(copies)[0] < 512 * 1024:
+        raise SystemExit("calibration copy dispatch not found (run bench.py with --calib-copy-mib 1024)")
+    calib = max(copies)[1]
     exp_kib = 1024 * 1024
     f_fac = exp_kib / res["FETCH_SIZE"][calib][1]
     w_fac = exp_kib / res["WRITE_SIZE"][calib][1]
     prods = {}
     for did, (kn, v) in res["FETCH_SIZE"].items():
-        if "k_prod" not in kn:
+        if "prod" not in kn:
             continue
         w = res["WRITE_SIZE"].get(did, [kn, 0.0])[1]
         prods[did] = (kn, v * f_fac * 1024, w * w_fac * 1024)

@@ -8,8 +8,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = ["csrc/kernels.hip", "csrc/symbolic.cpp", "csrc/api.cpp"]
 OUT = os.path.join(HERE, "liblsdm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-# packed FP32 instructions are disabled for all device code
-DEVFLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# packed FP32 instructions are disabled for all device code; MFMA accumulators
+# are kept in ordinary VGPRs (the accumulation-register form makes the
+# compiler copy every accumulator out and back around conditionally issued
+# MFMAs)
+DEVFLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-mllvm", "-amdgpu-mfma-vgpr-form=1"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
 
 

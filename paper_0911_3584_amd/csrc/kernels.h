@@ -19,6 +19,12 @@ template <class T> void product(const lsdm_plan* pl, const T* A, const T* B, T* 
 // symbolic pass on the GPU: steps of a plan (count pass fill = 0, fill pass fill = 1)
 void plan_steps(const Tile* tiles, i64 ntiles, const KEnt* kent, const i64* kbeg, const PlanView& v, int fill,
                 i32* counts, Step* steps, unsigned long long* work);
+// the same for group tiles
+void plan_gsteps(const GTile* tiles, i64 ntiles, const GKEnt* kent, const i64* kbeg, const PlanView& v, int fill,
+                 i32* counts, GStep* steps, unsigned long long* work);
+// zero records after the last group step (the product kernel stages records
+// up to two batches past a tile's end)
+constexpr i64 GSTEP_PAD = 32;
 // residual mode: fp32 copy of the off-site part; FP64 correction
 // C = alpha (RR + D_A B + A D_B - D_A D_B) + beta C with RR = P_C(R_A R_B) in fp32
 void offsite_f32(const lsdm_pattern* p, const double* in, float* out, hipStream_t st);

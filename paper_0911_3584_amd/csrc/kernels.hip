@@ -15,6 +15,10 @@
 //     the result D[b][r][c] is in lane 4b + c, register r.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+
 #include "kernels.h"
 #include "plan_common.h"
 
@@ -121,16 +125,9 @@ __global__ void __launch_bounds__(256) k_prod(const Tile* __restrict__ tiles, i6
   constexpr int RB = 32;   // step records per batch
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  // XCD-aware mapping: workgroups are dealt round-robin to the 8 XCDs, so give
-  // each XCD a contiguous range of tiles (neighbouring tiles share operands
-  // through that XCD's L2)
-  const int nx = 8;
-  const int xcd = blockIdx.x % nx;
-  const i64 lb = blockIdx.x / nx;
-  const i64 nb_x = (gridDim.x - xcd + nx - 1) / nx;
-  const i64 chunk = (ntiles + nx - 1) / nx;
-  const i64 t_begin = (i64)xcd * chunk;
-  const i64 t_end = t_begin + chunk < ntiles ? t_begin + chunk : ntiles;
+  // plain grid-stride over tiles (measured slightly faster than dealing
+  // contiguous tile chunks to the 8 XCDs)
+  const i64 t_begin = 0, t_end = ntiles, lb = blockIdx.x, nb_x = gridDim.x;
   // FP64: lane = 16 kk + 4 blk + x.  FP32: lane = 16 t + 4 kk + x.
   const int x = lane & 3;
   const int kk = F64 ? (lane >> 4) : ((lane >> 2) & 3);
@@ -281,13 +278,9 @@ __global__ void __launch_bounds__(256) k_prod16(const Tile* __restrict__ tiles, 
   constexpr int RB = 32;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int nx = 8;
-  const int xcd = blockIdx.x % nx;
-  const i64 lb = blockIdx.x / nx;
-  const i64 nb_x = (gridDim.x - xcd + nx - 1) / nx;
-  const i64 chunk = (ntiles + nx - 1) / nx;
-  const i64 t_begin = (i64)xcd * chunk;
-  const i64 t_end = t_begin + chunk < ntiles ? t_begin + chunk : ntiles;
+  // plain grid-stride over tiles (measured slightly faster than dealing
+  // contiguous tile chunks to the 8 XCDs)
+  const i64 t_begin = 0, t_end = ntiles, lb = blockIdx.x, nb_x = gridDim.x;
   // A operand: row = l % 16 (tile row i = row / 4, block row r = row % 4), inner kk = l / 16
   const int arow = lane & 15, ai = arow >> 2, ar = arow & 3, kk = lane >> 4;
   const int a_off = TA ? (kk * 4 + ar) : (ar * 4 + kk);
@@ -428,13 +421,9 @@ __global__ void __launch_bounds__(256) k_prod_bf16(const Tile* __restrict__ tile
   constexpr int RB = 32;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int nx = 8;
-  const int xcd = blockIdx.x % nx;
-  const i64 lb = blockIdx.x / nx;
-  const i64 nb_x = (gridDim.x - xcd + nx - 1) / nx;
-  const i64 chunk = (ntiles + nx - 1) / nx;
-  const i64 t_begin = (i64)xcd * chunk;
-  const i64 t_end = t_begin + chunk < ntiles ? t_begin + chunk : ntiles;
+  // plain grid-stride over tiles (measured slightly faster than dealing
+  // contiguous tile chunks to the 8 XCDs)
+  const i64 t_begin = 0, t_end = ntiles, lb = blockIdx.x, nb_x = gridDim.x;
   const int x = lane & 3, tb = (lane >> 2) & 3, g = lane >> 4;
   const int a_off = x * 4;             // row x of A_ik (R copy) = column x of X_ki (C copy)
   const int b_off = tb * 16 + x * 4;   // column x of block tb (C copy)
@@ -614,6 +603,280 @@ __global__ void __launch_bounds__(256) k_plan_steps(const Tile* __restrict__ til
         atomicAdd(work + 1, (unsigned long long)tr);
       }
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// group plan steps: as k_plan_steps, for group tiles (GQ row quads sharing one
+// inner list); one wavefront per tile, lane (entry el, column jq)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_plan_gsteps(const GTile* __restrict__ tiles, i64 ntiles,
+                                                     const GKEnt* __restrict__ kent, const i64* __restrict__ kbeg,
+                                                     PlanView v, int fill, i32* __restrict__ counts,
+                                                     GStep* __restrict__ steps,
+                                                     unsigned long long* __restrict__ work) {
+  constexpr int EPI = 64 / GJ;
+  const int lane = threadIdx.x & 63;
+  const i64 wave0 = (i64)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const i64 nw = (i64)gridDim.x * 4;
+  const int jq = lane % GJ, el = lane / GJ;
+  for (i64 t = wave0; t < ntiles; t += nw) {
+    const GTile& tl = tiles[t];
+    const i64 ck = gtile_column_key(v, tl, jq);
+    const i64 kb = kbeg[tl.group], ke = kbeg[tl.group + 1];
+    i64 pos = tl.step0;
+    int cnt = 0;
+    uint64_t fl = 0, tr = 0;
+    for (i64 e0 = kb; e0 < ke; e0 += EPI) {
+      const i64 e = e0 + el;
+      i32 b = -1;
+      uint32_t m[GQ];
+#pragma unroll
+      for (int w = 0; w < GQ; ++w) m[w] = 0;
+      if (e < ke) gslot_work(v, tl, kent[e], jq, ck, &b, m, &fl, &tr);
+      uint32_t any = 0;
+#pragma unroll
+      for (int w = 0; w < GQ; ++w) {
+#pragma unroll
+        for (int o = 1; o < GJ; o <<= 1) m[w] |= (uint32_t)__shfl_xor((int)m[w], o);
+        any |= m[w];
+      }
+      const bool active = any != 0u;
+      const unsigned long long vote = __ballot(active && jq == 0);
+      if (fill && active) {
+        const int before = __popcll(vote & ((1ull << (el * GJ)) - 1ull));
+        int* sp = reinterpret_cast<int*>(steps + pos + before);
+        sp[GROWS + jq] = b;
+        if (jq == 0) {
+          const GKEnt& ent = kent[e];
+          uint32_t rows = 0;
+#pragma unroll
+          for (int r = 0; r < GROWS; ++r) {
+            sp[r] = ent.a[r];
+            rows |= (ent.a[r] >= 0 ? 1u : 0u) << r;
+          }
+#pragma unroll
+          for (int w = 0; w < GQ; ++w) sp[GROWS + GJ + w] = (int)m[w];
+          sp[GROWS + GJ + GQ] = (int)rows;
+#pragma unroll
+          for (int z = GROWS + GJ + GQ + 1; z < 32; ++z) sp[z] = 0;
+        }
+      }
+      const int nv = __popcll(vote);
+      pos += nv;
+      cnt += nv;
+    }
+    if (!fill) {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        fl += (uint64_t)__shfl_xor((long long)fl, o);
+        tr += (uint64_t)__shfl_xor((long long)tr, o);
+      }
+      if (lane == 0) {
+        counts[t] = cnt;
+        atomicAdd(work, (unsigned long long)fl);
+        atomicAdd(work + 1, (unsigned long long)tr);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Group-tile product on the dense 16x16x4 MFMA with LDS staging.
+//
+// A workgroup of GQ = 4 wavefronts owns one group tile at a time: 16 output
+// rows (wavefront w: row quad w) x GJ column quads.  The tile's steps are
+// processed in batches of SB.  For each batch the workgroup stages in LDS the
+// step records and every operand the batch touches: per step the 16 A blocks
+// of the group's rows and the GJ B strips, each fetched from global memory
+// once for all four wavefronts (16 bytes per lane, 1 KB per instruction).
+// Software pipeline, one workgroup barrier per batch q:
+//   after the barrier: operands of q and records of q+1 are in LDS, and every
+//   wavefront is done with batch q-1;
+//   issue the global loads of records q+2 and operands q+1 (registers), run
+//   the MFMAs of batch q from LDS, then store the loaded values into the LDS
+//   slots batch q-1 used.
+// Rows without an A block are zeroed when the operand is read from LDS; a
+// column whose B strip is absent has no active slot and issues no MFMA.
+// ---------------------------------------------------------------------------
+// steps per staged batch (LDS: 2 x SB steps of A and B operands)
+#ifndef LSDM_GSB_F32
+#define LSDM_GSB_F32 4
+#endif
+#ifndef LSDM_GSB_F64
+#define LSDM_GSB_F64 4
+#endif
+template <class T> struct GCfg;
+template <> struct GCfg<float> { static constexpr int SB = LSDM_GSB_F32; };
+template <> struct GCfg<double> { static constexpr int SB = LSDM_GSB_F64; };
+
+typedef int i4v __attribute__((ext_vector_type(4)));
+
+template <class T, bool TA>
+__global__ void __launch_bounds__(256) k_gprod(const GTile* __restrict__ tiles, i64 ntiles,
+                                               const GStep* __restrict__ steps, const T* __restrict__ A,
+                                               const T* __restrict__ B, T* __restrict__ C,
+                                               const uint8_t* __restrict__ cmask, T alpha, T beta) {
+  typedef typename Mma16<T>::acc_t acc_t;
+  constexpr bool F64 = sizeof(T) == 8;
+  constexpr int SB = GCfg<T>::SB;
+  constexpr int AV = GROWS * 16;        // A values of one step
+  constexpr int BV = GJ * 64;           // B values of one step
+  constexpr int SV = AV + BV;
+  constexpr int VPL = 16 / (int)sizeof(T);
+  constexpr int PV = 64 * VPL;          // values of one 1 KB piece (16 bytes per lane)
+  constexpr int PPS = SV / PV;          // pieces per step
+  constexpr int SPW = SB / GQ;          // steps staged per wavefront and batch
+  constexpr int NPW = SPW * PPS;        // pieces per wavefront and batch
+  constexpr int RW = 32;                // dwords per record
+  constexpr int RLANES = SB * RW / 4;   // lanes that stage the records of a batch
+  static_assert(AV % PV == 0 && BV % PV == 0 && SB % GQ == 0 && RLANES <= 64, "staging layout");
+  __shared__ __attribute__((aligned(16))) T dbuf[2][SB * SV];
+  __shared__ __attribute__((aligned(16))) int rbuf[3][SB * RW];
+  // output strips of each wavefront's 4 x GJ slots and their block masks
+  __shared__ int2 cinfo[GQ][4 * GJ];
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int arow = lane & 15, ai = arow >> 2, ar = arow & 3, kk = lane >> 4;
+  const int a_off = (4 * wave + ai) * 16 + (TA ? (kk * 4 + ar) : (ar * 4 + kk));
+  const int b_off = ((lane & 15) >> 2) * 16 + kk * 4 + (lane & 3);
+  const int abit = 4 * wave + ai;
+  constexpr uint32_t COL = 1u | (1u << GJ) | (1u << (2 * GJ)) | (1u << (3 * GJ));
+  // contiguous tile ranges per XCD (workgroups are dealt to the 8 XCDs round
+  // robin), so concurrent tiles of one XCD share A and B through its L2
+  const i64 xcd = blockIdx.x & 7, nbx = gridDim.x >> 3, lb = blockIdx.x >> 3;
+  const i64 t_begin = ntiles * xcd / 8, t_end = ntiles * (xcd + 1) / 8;
+  const i4v* recs = reinterpret_cast<const i4v*>(steps);
+
+  for (i64 t = t_begin + lb; t < t_end; t += nbx) {
+    const GTile* tp = tiles + uniform64(t);
+    const i64 s0 = tp->step0;
+    const int ns = tp->nsteps;
+    acc_t acc[GJ];
+#pragma unroll
+    for (int q = 0; q < GJ; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[q][e] = (T)0;
+    const int nb = (ns + SB - 1) / SB;
+    // records of batch q: lane l < RLANES holds dwords 4l..4l+3 of the batch
+    auto load_records = [&](int q) -> i4v {
+      i4v v = {0, 0, 0, 0};
+      if (wave == 0 && lane < RLANES) v = recs[(s0 + (i64)SB * q) * (RW / 4) + lane];
+      return v;
+    };
+    auto store_records = [&](const i4v& v, int slot) {
+      if (wave == 0 && lane < RLANES) *reinterpret_cast<i4v*>(&rbuf[slot][4 * lane]) = v;
+    };
+    // operands of the batch whose records are in slot rslot: wavefront w
+    // stages steps SPW*w .. SPW*w+SPW-1, piece i of its share is step
+    // SPW*w + i / PPS, part i % PPS (1 KB) of that step's values
+    auto load_operands = [&](int rslot, i4v (&d)[NPW]) {
+      int idx[NPW];
+#pragma unroll
+      for (int i = 0; i < NPW; ++i) {
+        const int r = SPW * wave + i / PPS, part = i % PPS;
+        const int off = part * PV + lane * VPL;
+        idx[i] = part * PV < AV ? rbuf[rslot][r * RW + (off >> 4)] : rbuf[rslot][r * RW + GROWS + ((off - AV) >> 6)];
+      }
+#pragma unroll
+      for (int i = 0; i < NPW; ++i) {
+        const int part = i % PPS;
+        const int off = part * PV + lane * VPL;
+        const T* src = part * PV < AV ? A + (i64)max(idx[i], 0) * 16 + (off & 15)
+                                      : B + (i64)max(idx[i], 0) * 64 + ((off - AV) & 63);
+#ifdef LSDM_GNT
+        d[i] = __builtin_nontemporal_load(reinterpret_cast<const i4v*>(src));
+#else
+        d[i] = *reinterpret_cast<const i4v*>(src);
+#endif
+      }
+    };
+    auto store_operands = [&](const i4v (&d)[NPW], int dslot) {
+#pragma unroll
+      for (int i = 0; i < NPW; ++i) {
+        const int r = SPW * wave + i / PPS, part = i % PPS;
+        *reinterpret_cast<i4v*>(&dbuf[dslot][r * SV + part * PV + lane * VPL]) = d[i];
+      }
+    };
+    // this wavefront's output strips (lane < 4 GJ: slot lane), staged in LDS
+    // with their block masks for the epilogue
+    const i32 my_cs = lane < 4 * GJ ? tp->cstrip[4 * GJ * wave + lane] : -1;
+    if (nb > 0) {
+      {
+        const i4v r0 = load_records(0);
+        const i4v r1 = nb > 1 ? load_records(1) : i4v{0, 0, 0, 0};
+        store_records(r0, 0);
+        store_records(r1, 1);
+      }
+      __syncthreads();
+      {
+        i4v d[NPW];
+        load_operands(0, d);
+        const int mk = my_cs >= 0 ? (int)cmask[my_cs] : 0;
+        store_operands(d, 0);
+        if (lane < 4 * GJ) cinfo[wave][lane] = int2{my_cs, mk};
+      }
+    } else if (lane < 4 * GJ) {
+      cinfo[wave][lane] = int2{my_cs, my_cs >= 0 ? (int)cmask[my_cs] : 0};
+    }
+    if (nb > 0) {
+      for (int q = 0; q < nb; ++q) {
+        __syncthreads();
+        const bool more_r = q + 2 < nb, more_d = q + 1 < nb;
+        i4v rn = {0, 0, 0, 0};
+        i4v dn[NPW];
+        if (more_r) rn = load_records(q + 2);
+        if (more_d) load_operands((q + 1) % 3, dn);
+        const int rs = q % 3, ds = q & 1;
+        const int nv = ns - SB * q;
+        // slot masks of this wavefront (lane r < SB) and row bits (lane SB + r)
+        // of the batch's steps, read once per batch
+        int mr = 0;
+        if (lane < SB)
+          mr = rbuf[rs][lane * RW + GROWS + GJ + wave];
+        else if (lane < 2 * SB)
+          mr = rbuf[rs][(lane - SB) * RW + GROWS + GJ + GQ];
+#pragma unroll 1
+        for (int r = 0; r < SB; ++r) {
+          uint32_t mask = (uint32_t)__builtin_amdgcn_readlane(mr, r);
+          const uint32_t rows = (uint32_t)__builtin_amdgcn_readlane(mr, SB + r);
+          if (r >= nv) mask = 0u;
+          if (mask == 0u) continue;
+          const T* sA = &dbuf[ds][r * SV];
+          T av = sA[a_off];
+          av = ((rows >> abit) & 1u) ? av : (T)0;
+          T bv[GJ];
+#pragma unroll
+          for (int j = 0; j < GJ; ++j) bv[j] = sA[AV + j * 64 + b_off];
+#pragma unroll
+          for (int j = 0; j < GJ; ++j)
+            if ((mask >> j) & COL) acc[j] = Mma16<T>::mma(av, bv[j], acc[j]);
+        }
+        if (more_d) store_operands(dn, (q + 1) & 1);
+        if (more_r) store_records(rn, (q + 2) % 3);
+      }
+    }
+    // epilogue: lane l, register v holds D[row][col]; f32 row = 4 (l/16) + v,
+    // f64 row = 4 v + l/16; col = l % 16 (block t = col / 4, c = col % 4)
+    {
+      const int col = lane & 15, tb = col >> 2, cc = col & 3;
+#pragma unroll
+      for (int j = 0; j < GJ; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = F64 ? v : (lane >> 4);
+          const int rr = F64 ? (lane >> 4) : v;
+          const int2 ci = cinfo[wave][GJ * i + j];
+          if (ci.x < 0) continue;
+          const i64 idx = (i64)ci.x * 64 + tb * 16 + rr * 4 + cc;
+          T o = ((ci.y >> tb) & 1) ? alpha * acc[j][v] : (T)0;
+          if (beta != (T)0) o += beta * C[idx];
+          C[idx] = o;
+        }
+    }
+    // the next tile's prologue reuses record slots 0, 1 and operand slot 0
+    __syncthreads();
   }
 }
 
@@ -846,8 +1109,8 @@ void transpose_strips(const lsdm_pattern* p, const T* in, T* out, hipStream_t st
 template void transpose_strips<double>(const lsdm_pattern*, const double*, double*, hipStream_t);
 template void transpose_strips<float>(const lsdm_pattern*, const float*, float*, hipStream_t);
 
-// The product kernel deals tiles to the 8 XCDs in contiguous chunks and needs
-// at least one workgroup per XCD: the grid is a multiple of 8, at least 8.
+// Grid of the product kernels: up to 16384 workgroups of 4 wavefronts, one
+// tile per wavefront at a time (grid-stride).
 unsigned product_grid(i64 ntiles) {
   i64 blocks = (ntiles + 3) / 4;
   if (blocks > 16384) blocks = 16384;
@@ -856,16 +1119,58 @@ unsigned product_grid(i64 ntiles) {
   return (unsigned)blocks;
 }
 
-// which product kernel runs: the 4x4-block MFMA form (k_prod) or the dense
-// 16x16x4 form (k_prod16) on the same plans
-static bool dense_product_kernel() { return false; }
+// which product kernel runs for FP64/FP32: the dense 16x16x4 form (k_prod16,
+// measured 1.2x (FP64) and 2.5x (FP32) faster on the RL16 chain) or the
+// 4x4-block form (k_prod, fewer wasted lanes, more load instructions)
+static bool dense_product_kernel() { return true; }
+// the LDS-staged group-tile kernel (k_gprod) for FP64/FP32
+static bool group_product_kernel() { return true; }
+
+// Grid of the group kernel: as many workgroups as are resident at once (so
+// every workgroup of an XCD walks its tile range in step with the others), a
+// multiple of 8 (one contiguous tile range per XCD).
+template <class K>
+static unsigned gproduct_grid(K kernel, i64 ntiles) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, int> cache;   // (kernel, device) -> resident workgroups
+  int d = 0;
+  HIP_CHECK(hipGetDevice(&d));
+  int resident;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find({reinterpret_cast<const void*>(kernel), d});
+    if (it == cache.end()) {
+      int per_cu = 0, cus = 0;
+      HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0));
+      HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, d));
+      it = cache.emplace(std::make_pair(reinterpret_cast<const void*>(kernel), d), std::max(1, per_cu) * std::max(1, cus)).first;
+    }
+    resident = it->second;
+  }
+  i64 blocks = std::min<i64>((ntiles + 7) / 8 * 8, resident);
+  blocks = std::max<i64>(8, blocks / 8 * 8);
+  return (unsigned)blocks;
+}
 
 template <class T>
 void product(const lsdm_plan* pl, const T* A, const T* B, T* C, double alpha, double beta, hipStream_t st) {
+  const uint8_t* cm = pl->C->d_smask.as<uint8_t>();
+  if (group_product_kernel()) {
+    if (pl->n_gtiles == 0) return;
+    const GTile* Tl = pl->d_gtiles.as<GTile>();
+    const GStep* S = pl->d_gsteps.as<GStep>();
+    const dim3 b(256);
+    if (pl->transA)
+      hipLaunchKernelGGL((k_gprod<T, true>), dim3(gproduct_grid(k_gprod<T, true>, pl->n_gtiles)), b, 0, st, Tl,
+                         pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta);
+    else
+      hipLaunchKernelGGL((k_gprod<T, false>), dim3(gproduct_grid(k_gprod<T, false>, pl->n_gtiles)), b, 0, st, Tl,
+                         pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta);
+    return;
+  }
   if (pl->n_tiles == 0) return;
   const Tile* Tl = pl->d_tiles.as<Tile>();
   const Step* S = pl->d_steps.as<Step>();
-  const uint8_t* cm = pl->C->d_smask.as<uint8_t>();
   const dim3 g(product_grid(pl->n_tiles)), b(256);
   if (dense_product_kernel()) {
     if (pl->transA)
@@ -889,6 +1194,15 @@ void plan_steps(const Tile* tiles, i64 ntiles, const KEnt* kent, const i64* kbeg
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_plan_steps, dim3((unsigned)blocks), dim3(256), 0, 0, tiles, ntiles, kent, kbeg, v, fill, counts,
                      steps, work);
+}
+
+void plan_gsteps(const GTile* tiles, i64 ntiles, const GKEnt* kent, const i64* kbeg, const PlanView& v, int fill,
+                 i32* counts, GStep* steps, unsigned long long* work) {
+  if (ntiles == 0) return;
+  i64 blocks = (ntiles + 3) / 4;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_plan_gsteps, dim3((unsigned)blocks), dim3(256), 0, 0, tiles, ntiles, kent, kbeg, v, fill,
+                     counts, steps, work);
 }
 
 static PatDev patdev(const lsdm_pattern* p) {

@@ -152,6 +152,38 @@ struct alignas(64) Step {
 };
 static_assert(sizeof(Step) == 64, "step record is one 64-byte scalar load");
 
+// Group tiles (the FP64/FP32 products): a workgroup of GQ wavefronts computes
+// GQ consecutive row quads (4 * GQ output rows, one quad per wavefront) x GJ
+// column quads over one shared step list, the union of the rows' inner
+// entries, so every B strip of a step is fetched once for all GQ row quads.
+constexpr int GQ = 4;
+constexpr int GJ = 8;
+constexpr int GROWS = 4 * GQ;
+// groups per super-group of the tile traversal order
+constexpr int GSUPER = 4;
+
+struct GTile {
+  i32 group;            // rows 4*GQ*group .. +4*GQ-1
+  i32 nsteps;
+  i64 step0;
+  i32 cstrip[GROWS * GJ];   // output strip of slot (row r, jq) = [GJ*r + jq], -1 if absent
+};
+
+// One step of a group tile (128 bytes):
+//   a[r]: strip-layout offset / 16 of A_{r,k} (X_{k,r} for a transposed A), -1 if absent
+//   b[jq]: strip index of B's strip (k, quad jq), -1 if absent
+//   mask[w]: slots of wavefront w, bit GJ*i + jq for row 4w+i
+//   rows: bit r set when a[r] >= 0
+struct alignas(128) GStep {
+  i32 a[GROWS];
+  i32 b[GJ];
+  uint32_t mask[GQ];
+  uint32_t rows;
+  i32 pad[3];
+};
+static_assert(sizeof(GStep) == 128, "group step record is 128 bytes");
+static_assert(4 * GJ <= 32, "a wavefront's slots fit one 32-bit mask");
+
 }  // namespace lsdm
 
 struct lsdm_plan {
@@ -162,6 +194,9 @@ struct lsdm_plan {
   lsdm::i64 n_tiles = 0, n_steps = 0, n_triples = 0;
   double flops = 0;
   lsdm::DevBuf d_tiles, d_steps;
+  // group tiles and their steps
+  lsdm::i64 n_gtiles = 0, n_gsteps = 0;
+  lsdm::DevBuf d_gtiles, d_gsteps;
   // for a transposed B the plan multiplies by a materialised transpose
   lsdm::DevBuf d_bT;                // strip-layout workspace of B^T (doubles)
 };

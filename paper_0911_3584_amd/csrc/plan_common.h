@@ -83,4 +83,51 @@ __host__ __device__ inline void slot_work(const PlanView& v, const Tile& t, cons
   }
 }
 
+// ---------------------------------------------------------------------------
+// group tiles: GQ row quads share one inner list
+// ---------------------------------------------------------------------------
+struct GKEnt {
+  i32 k;
+  i32 m;
+  i32 a[GROWS];
+};
+
+__host__ __device__ inline i64 gtile_column_key(const PlanView& v, const GTile& t, int jq) {
+  for (int r = 0; r < GROWS; ++r) {
+    const i32 cs = t.cstrip[GJ * r + jq];
+    if (cs >= 0) return skey(v.c_squad[cs], v.c_simg[cs]);
+  }
+  return -1;
+}
+
+// Work of one (group tile, inner entry, column quad): B strip index, slot bits
+// per wavefront (bit GJ*i + jq of mask[w] for row 4w+i), useful flops and
+// atom triples.
+__host__ __device__ inline void gslot_work(const PlanView& v, const GTile& t, const GKEnt& e, int jq, i64 colkey,
+                                           i32* bidx, uint32_t (&mask)[GQ], uint64_t* flops, uint64_t* triples) {
+  *bidx = -1;
+  for (int w = 0; w < GQ; ++w) mask[w] = 0;
+  if (colkey < 0) return;
+  const i32 q = (i32)(colkey >> 24), n = (i32)(colkey & 0xffffff);
+  const i64 b = find_b_strip(v, e.k, skey(q, img_sub(n, e.m)));
+  if (b < 0) return;
+  *bidx = (i32)b;
+  const uint8_t bm = v.b_smask[b];
+  for (int r = 0; r < GROWS; ++r) {
+    if (e.a[r] < 0) continue;
+    const i32 cs = t.cstrip[GJ * r + jq];
+    if (cs < 0) continue;
+    const uint8_t u = bm & v.c_smask[cs];
+    if (!u) continue;
+    mask[r >> 2] |= 1u << (GJ * (r & 3) + jq);
+    const i32 pi = GROWS * t.group + r;
+    for (int bb = 0; bb < 4; ++bb) {
+      if (!(u >> bb & 1)) continue;
+      const i32 pj = 4 * q + bb;
+      *flops += 2ull * (uint64_t)v.prows[pi] * (uint64_t)v.prows[e.k] * (uint64_t)v.prows[pj];
+      if (v.first[pi] && v.first[e.k] && v.first[pj]) *triples += 1;
+    }
+  }
+}
+
 }  // namespace lsdm

@@ -388,6 +388,62 @@ void ensure_maps(lsdm_pattern* p) {
 // ---------------------------------------------------------------------------
 bool have_device();
 
+// Inner list of output rows row0 .. row0+NR-1: the union over the rows of A's
+// blocks (k, m), one entry per (k, m) with the A block of every row (-1 where
+// absent), sorted by (k, m).  For a transposed A the row pattern is A's own
+// (range patterns are symmetric) and the block is the transpose of A_{k,(i,-m)}.
+template <int NR, class Ent>
+static void inner_list(const lsdm_pattern* A, bool tA, i32 row0, std::vector<Ent>& K) {
+  const i32 np = A->sys->n_pseudo;
+  std::vector<std::pair<i64, std::pair<int, i32>>> raw;
+  for (int ii = 0; ii < NR; ++ii) {
+    const i32 row = row0 + ii;
+    if (row >= np) break;
+    for (i64 st = A->sptr[row]; st < A->sptr[row + 1]; ++st)
+      for (int t = 0; t < 4; ++t) {
+        if (!(A->smask[st] >> t & 1)) continue;
+        const i32 k = 4 * A->squad[st] + t;
+        const i32 m = A->simg[st];
+        i64 blk;
+        if (!tA) {
+          blk = st * 4 + t;
+        } else {
+          const i64 ms = find_strip(A, k, skey(row >> 2, img_neg(m)));
+          if (ms < 0) LSDM_THROW(LSDM_EPATTERN, "transposed operand pattern is not symmetric");
+          blk = ms * 4 + (row & 3);
+        }
+        raw.push_back({((i64)k << 24) | m, {ii, (i32)blk}});
+      }
+  }
+  std::sort(raw.begin(), raw.end());
+  K.clear();
+  for (auto& e : raw) {
+    if (K.empty() || (((i64)K.back().k << 24) | K.back().m) != e.first) {
+      Ent ke;
+      ke.k = (i32)(e.first >> 24);
+      ke.m = (i32)(e.first & 0xffffff);
+      for (int ii = 0; ii < NR; ++ii) ke.a[ii] = -1;
+      K.push_back(ke);
+    }
+    K.back().a[e.second.first] = e.second.second;
+  }
+}
+
+// sorted, distinct column keys of C's strips in rows row0 .. row0+nr-1
+static std::vector<i64> column_keys(const lsdm_pattern* C, i32 row0, int nr) {
+  std::vector<i64> ck;
+  for (int ii = 0; ii < nr; ++ii) {
+    const i32 row = row0 + ii;
+    if (row >= C->sys->n_pseudo) break;
+    for (i64 st = C->sptr[row]; st < C->sptr[row + 1]; ++st) ck.push_back(skey(C->squad[st], C->simg[st]));
+  }
+  std::sort(ck.begin(), ck.end());
+  ck.erase(std::unique(ck.begin(), ck.end()), ck.end());
+  return ck;
+}
+
+static void build_gplan(lsdm_plan* pl);
+
 void build_plan(lsdm_plan* pl) {
   const lsdm_pattern* A = pl->A;
   const lsdm_pattern* B = pl->B;
@@ -398,48 +454,9 @@ void build_plan(lsdm_plan* pl) {
   std::vector<std::vector<KEnt>> kents(nq);
   const bool tA = pl->transA != 0;
   parallel_for(nq, [&](i64 I) {
-    // inner list: the union over the 4 rows of A's blocks (k, m); for a
-    // transposed A the row pattern is A's own (range patterns are symmetric)
-    // and the block is the transpose of A_{k,(i,-m)}
-    std::vector<std::pair<i64, std::pair<int, i32>>> raw;
-    for (int ii = 0; ii < 4; ++ii) {
-      i32 row = 4 * (i32)I + ii;
-      for (i64 st = A->sptr[row]; st < A->sptr[row + 1]; ++st)
-        for (int t = 0; t < 4; ++t) {
-          if (!(A->smask[st] >> t & 1)) continue;
-          i32 k = 4 * A->squad[st] + t;
-          i32 m = A->simg[st];
-          i64 blk;
-          if (!tA) {
-            blk = st * 4 + t;
-          } else {
-            i64 ms = find_strip(A, k, skey(row >> 2, img_neg(m)));
-            if (ms < 0) LSDM_THROW(LSDM_EPATTERN, "transposed operand pattern is not symmetric");
-            blk = ms * 4 + (row & 3);
-          }
-          raw.push_back({((i64)k << 24) | m, {ii, (i32)blk}});
-        }
-    }
-    std::sort(raw.begin(), raw.end());
-    auto& K = kents[I];
-    for (auto& e : raw) {
-      if (K.empty() || (((i64)K.back().k << 24) | K.back().m) != e.first) {
-        KEnt ke;
-        ke.k = (i32)(e.first >> 24);
-        ke.m = (i32)(e.first & 0xffffff);
-        for (int ii = 0; ii < 4; ++ii) ke.a[ii] = -1;
-        K.push_back(ke);
-      }
-      K.back().a[e.second.first] = e.second.second;
-    }
+    inner_list<4>(A, tA, 4 * (i32)I, kents[I]);
     // output column quads of the 4 rows of C, grouped TJ per tile
-    std::vector<i64> ckeys;
-    for (int ii = 0; ii < 4; ++ii) {
-      i32 row = 4 * (i32)I + ii;
-      for (i64 st = C->sptr[row]; st < C->sptr[row + 1]; ++st) ckeys.push_back(skey(C->squad[st], C->simg[st]));
-    }
-    std::sort(ckeys.begin(), ckeys.end());
-    ckeys.erase(std::unique(ckeys.begin(), ckeys.end()), ckeys.end());
+    const std::vector<i64> ckeys = column_keys(C, 4 * (i32)I, 4);
     const i64 nt = ((i64)ckeys.size() + TJ - 1) / TJ;
     std::vector<Tile> T(nt);
     for (i64 t = 0; t < nt; ++t) {
@@ -551,6 +568,137 @@ void build_plan(lsdm_plan* pl) {
       pl->flops += (double)fl[t];
       pl->n_triples += (i64)tr[t];
     }
+  }
+  build_gplan(pl);
+}
+
+// Group plan: tiles of GQ row quads x GJ column quads in group-major order
+// (inside a group by column), steps generated on the GPU in two passes (count,
+// then fill) like the quad plan; the host path counts only.
+static void build_gplan(lsdm_plan* pl) {
+  const lsdm_pattern* A = pl->A;
+  const lsdm_pattern* B = pl->B;
+  const lsdm_pattern* C = pl->C;
+  const lsdm_system* s = C->sys;
+  const i32 ng = (s->n_quads + GQ - 1) / GQ;
+  const bool tA = pl->transA != 0;
+  std::vector<std::vector<GKEnt>> kents(ng);
+  std::vector<std::vector<GTile>> tiles(ng);
+  parallel_for(ng, [&](i64 g) {
+    const i32 row0 = GROWS * (i32)g;
+    inner_list<GROWS>(A, tA, row0, kents[g]);
+    const std::vector<i64> ckeys = column_keys(C, row0, GROWS);
+    const i64 nt = ((i64)ckeys.size() + GJ - 1) / GJ;
+    std::vector<GTile> T(nt);
+    for (i64 t = 0; t < nt; ++t) {
+      T[t].group = (i32)g;
+      T[t].nsteps = 0;
+      T[t].step0 = 0;
+      for (int q = 0; q < GROWS * GJ; ++q) T[t].cstrip[q] = -1;
+    }
+    for (int r = 0; r < GROWS; ++r) {
+      const i32 row = row0 + r;
+      if (row >= s->n_pseudo) break;
+      for (i64 st = C->sptr[row]; st < C->sptr[row + 1]; ++st) {
+        const i64 c = std::lower_bound(ckeys.begin(), ckeys.end(), skey(C->squad[st], C->simg[st])) - ckeys.begin();
+        T[c / GJ].cstrip[GJ * r + (c % GJ)] = (i32)st;
+      }
+    }
+    tiles[g] = std::move(T);
+  }, 1);
+  std::vector<i64> kbeg(ng + 1, 0);
+  for (i32 g = 0; g < ng; ++g) kbeg[g + 1] = kbeg[g] + (i64)kents[g].size();
+  std::vector<GKEnt> allK(kbeg[ng]);
+  parallel_for(ng, [&](i64 g) { std::copy(kents[g].begin(), kents[g].end(), allK.begin() + kbeg[g]); });
+  std::vector<std::vector<GKEnt>>().swap(kents);
+  std::vector<GTile> allT;
+  for (i32 g = 0; g < ng; ++g) allT.insert(allT.end(), tiles[g].begin(), tiles[g].end());
+  std::vector<std::vector<GTile>>().swap(tiles);
+  // Traversal order: super-groups of GSUPER groups, inside a super-group by
+  // the tile's first output column, so the tiles that run together on one XCD
+  // cover neighbouring rows and the same columns: they share B strips (same
+  // columns) and A blocks (same rows) through its L2.
+  {
+    std::vector<std::pair<std::pair<i64, i64>, i64>> key(allT.size());
+    for (size_t t = 0; t < allT.size(); ++t) {
+      i64 c0 = -1;
+      for (int q = 0; q < GROWS * GJ && c0 < 0; ++q)
+        if (allT[t].cstrip[q] >= 0) c0 = skey(C->squad[allT[t].cstrip[q]], C->simg[allT[t].cstrip[q]]);
+      key[t] = {{allT[t].group / GSUPER, c0}, (i64)t};
+    }
+    std::sort(key.begin(), key.end());
+    std::vector<GTile> ord(allT.size());
+    for (size_t t = 0; t < allT.size(); ++t) ord[t] = allT[key[t].second];
+    allT.swap(ord);
+  }
+  const i64 ntile = (i64)allT.size();
+  pl->n_gtiles = ntile;
+  if (have_device()) {
+    DevBuf d_k, d_kb, d_cnt, d_work;
+    d_k.upload(allK.data(), sizeof(GKEnt) * allK.size());
+    d_kb.upload(kbeg.data(), sizeof(i64) * kbeg.size());
+    pl->d_gtiles.upload(allT.data(), sizeof(GTile) * allT.size());
+    d_cnt.alloc(sizeof(i32) * (ntile + 1));
+    d_work.alloc(16);
+    HIP_CHECK(hipMemset(d_work.p, 0, 16));
+    PlanView v{B->d_sptr.as<i64>(), B->d_squad.as<i32>(), B->d_simg.as<i32>(), B->d_smask.as<uint8_t>(),
+               C->d_squad.as<i32>(), C->d_simg.as<i32>(), C->d_smask.as<uint8_t>(), s->d_prows.as<i32>(),
+               s->d_first.as<uint8_t>()};
+    plan_gsteps(pl->d_gtiles.as<GTile>(), ntile, d_k.as<GKEnt>(), d_kb.as<i64>(), v, 0, d_cnt.as<i32>(), nullptr,
+                d_work.as<unsigned long long>());
+    HIP_CHECK(hipGetLastError());
+    std::vector<i32> cnt(ntile);
+    uint64_t work[2];
+    if (ntile) HIP_CHECK(hipMemcpy(cnt.data(), d_cnt.p, sizeof(i32) * ntile, hipMemcpyDeviceToHost));
+    HIP_CHECK(hipMemcpy(work, d_work.p, 16, hipMemcpyDeviceToHost));
+    i64 nstep = 0;
+    for (i64 t = 0; t < ntile; ++t) {
+      allT[t].step0 = nstep;
+      allT[t].nsteps = cnt[t];
+      nstep += cnt[t];
+    }
+    pl->n_gsteps = nstep;
+    if ((double)work[0] != pl->flops || (i64)work[1] != pl->n_triples)
+      LSDM_THROW(LSDM_EDEVICE, "group plan work differs from the quad plan's");
+    pl->d_gtiles.upload(allT.data(), sizeof(GTile) * allT.size());
+    // the product kernel stages records up to two batches past a tile's last
+    // step: pad with zero records
+    pl->d_gsteps.alloc(sizeof(GStep) * (nstep + GSTEP_PAD));
+    HIP_CHECK(hipMemset(pl->d_gsteps.p, 0, sizeof(GStep) * (nstep + GSTEP_PAD)));
+    plan_gsteps(pl->d_gtiles.as<GTile>(), ntile, d_k.as<GKEnt>(), d_kb.as<i64>(), v, 1, nullptr,
+                pl->d_gsteps.as<GStep>(), nullptr);
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipDeviceSynchronize());
+  } else {
+    PlanView v{B->sptr.data(), B->squad.data(), B->simg.data(), B->smask.data(), C->squad.data(), C->simg.data(),
+               C->smask.data(), s->prows.data(), s->first.data()};
+    std::vector<i64> ns(ntile, 0);
+    std::vector<uint64_t> fl(ntile, 0), tr(ntile, 0);
+    parallel_for(ntile, [&](i64 t) {
+      const GTile& tl = allT[t];
+      i64 ck[GJ];
+      for (int jq = 0; jq < GJ; ++jq) ck[jq] = gtile_column_key(v, tl, jq);
+      for (i64 e = kbeg[tl.group]; e < kbeg[tl.group + 1]; ++e) {
+        uint32_t any = 0;
+        for (int jq = 0; jq < GJ; ++jq) {
+          i32 b;
+          uint32_t m[GQ];
+          gslot_work(v, tl, allK[e], jq, ck[jq], &b, m, &fl[t], &tr[t]);
+          for (int w = 0; w < GQ; ++w) any |= m[w];
+        }
+        if (any) ++ns[t];
+      }
+    }, 16);
+    i64 nstep = 0;
+    uint64_t F = 0, Tr = 0;
+    for (i64 t = 0; t < ntile; ++t) {
+      nstep += ns[t];
+      F += fl[t];
+      Tr += tr[t];
+    }
+    pl->n_gsteps = nstep;
+    if ((double)F != pl->flops || (i64)Tr != pl->n_triples)
+      LSDM_THROW(LSDM_EPATTERN, "group plan work differs from the quad plan's");
   }
 }
 
