@@ -71,11 +71,12 @@ def profile_mode(lnv, inp, prec, steps):
 
 def cpu_baseline(cfg, flops_per_atom):
     """The oracle (FP64 C++/OpenMP, untuned) on a bounded sample of the same
-    workload: the 2x2x2-cell periodic crystal with the same ranges, whose
-    per-atom work equals the large cell's (translation invariance)."""
+    workload: the 12x12x12-cell (13824-atom) periodic crystal with the same
+    ranges, whose per-atom work equals the 32768-atom cell's (translation
+    invariance); about 10-30 s of host time."""
     import oracle
     import workloads
-    s = workloads.diamond(2)
+    s = workloads.diamond(12)
     rS, rH, rL = cfg["rS"], cfg["rH"], cfg["rL"]
     inp = oracle.make_inputs(s, rS, rH, rL)
     t0 = time.perf_counter()
@@ -84,7 +85,7 @@ def cpu_baseline(cfg, flops_per_atom):
     dt = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": round(flops_per_atom * s.n / dt / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 oracle E + dE/dL of the 64-atom 2x2x2 periodic cell at the same ranges "
+            "sample": f"FP64 oracle E + dE/dL of the 13824-atom 12x12x12 periodic cell at the same ranges "
                       f"({dt:.2f} s; same per-atom work as the full cell), equivalent useful GFLOP/s",
             "seconds": round(dt, 3), "energy_per_atom": r["E"] / s.n}
 

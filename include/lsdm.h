@@ -103,8 +103,11 @@ void lsdm_pattern_destroy(lsdm_pattern* p);
  * projected on C's pattern (C's range is the truncation), op = transpose when
  * the flag is 1.  A transposed operand uses A's pattern mirrored
  * ((i,j,n) -> (j,i,-n)).  The plan holds the task list of block triples
- * (i,k,j) grouped into tiles and steps for the GPU kernels; it is built on the
- * host (multithreaded) and kept on the device.
+ * (i,k,j) grouped into tiles (16 output rows x 32 output columns of pseudo-
+ * atoms) and steps (one inner pseudo-atom k of a tile) for the GPU kernels:
+ * the tiles and their inner lists are built on the host (multithreaded), the
+ * steps are generated and kept on the device.  Without a device only the
+ * counts are computed (plan_info works, products fail with LSDM_EDEVICE).
  * Errors: LSDM_EPATTERN (patterns of different systems), LSDM_ENOMEM. */
 int lsdm_plan_create(const lsdm_pattern* A, int transA, const lsdm_pattern* B, int transB,
                      const lsdm_pattern* C, lsdm_plan** out);

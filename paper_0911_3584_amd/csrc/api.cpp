@@ -578,7 +578,7 @@ int lsdm_plan_info(const lsdm_plan* pl, int64_t* n_triples, double* flops, int64
     if (!pl) LSDM_THROW(LSDM_EINVAL, "null plan");
     if (n_triples) *n_triples = pl->n_triples;
     if (flops) *flops = pl->flops;
-    if (plan_bytes) *plan_bytes = (int64_t)(pl->n_tiles * sizeof(Tile) + pl->n_steps * sizeof(Step));
+    if (plan_bytes) *plan_bytes = (int64_t)(pl->n_gtiles * sizeof(GTile) + pl->n_gsteps * sizeof(GStep));
   });
 }
 

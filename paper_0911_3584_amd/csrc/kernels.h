@@ -17,9 +17,6 @@ template <class T> void transpose_strips(const lsdm_pattern* p, const T* in, T* 
 // C = alpha P_C(op(A) B) + beta C in strip layout (B already transposed if the plan says so)
 template <class T> void product(const lsdm_plan* pl, const T* A, const T* B, T* C, double alpha, double beta, hipStream_t st);
 // symbolic pass on the GPU: steps of a plan (count pass fill = 0, fill pass fill = 1)
-void plan_steps(const Tile* tiles, i64 ntiles, const KEnt* kent, const i64* kbeg, const PlanView& v, int fill,
-                i32* counts, Step* steps, unsigned long long* work);
-// the same for group tiles
 void plan_gsteps(const GTile* tiles, i64 ntiles, const GKEnt* kent, const i64* kbeg, const PlanView& v, int fill,
                  i32* counts, GStep* steps, unsigned long long* work);
 // zero records after the last group step (the product kernel stages records

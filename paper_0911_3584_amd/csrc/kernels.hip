@@ -3,16 +3,13 @@
 //  * layout conversion between the caller's block layout and the internal
 //    strip layout (gather/scatter of 4x4 sub-blocks);
 //  * strip-layout transpose (B^T for products with a transposed B);
+//  * the symbolic step generation of product plans;
 //  * the truncated block product C = alpha P_C(op(A) B) + beta C on MFMA:
-//    one wavefront per tile of 4 output rows x 4 output column quads, 16
-//    accumulator slots, one MFMA per active (row, column quad) slot per step;
-//  * K assembly (eq. 3) and a bitwise-reproducible compensated FP64 dot.
-//
-// MFMA lane maps used below (measured on gfx950):
-//   v_mfma_f64_4x4x4_4b_f64: lane l = 16k + 4b + x holds A[b][x][k] and
-//     B[b][k][x]; the result D[b][r][c] is in lane 16r + 4b + c.
-//   v_mfma_f32_4x4x1_16b_f32: lane l = 4b + x holds A[b][x][0] and B[b][0][x];
-//     the result D[b][r][c] is in lane 4b + c, register r.
+//    one workgroup per group tile of 16 output rows x GJ output column quads,
+//    operands staged in LDS, one 16x16 MFMA per active (row quad, column quad)
+//    slot and step (FP64, FP32) or per 4 steps (BF16);
+//  * the residual-mode FP64 corrections, K assembly (eq. 3) and a
+//    bitwise-reproducible compensated FP64 dot.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -78,179 +75,8 @@ __global__ void k_transpose_strips(const T* __restrict__ in, T* __restrict__ out
 }
 
 // ---------------------------------------------------------------------------
-// truncated block product C = alpha P_C(op(A) B) + beta C
-//
-// One wavefront per tile of 4 output rows x TJ output column quads; slot
-// (i, jq) accumulates the output strip (row i, column quad jq).  Each step of
-// the tile is one inner pseudo-atom k: up to 4 blocks A_{i,k} and TJ strips
-// B_{k,jq}, and a mask of the slots with useful work.  Step records are
-// wave-uniform (scalar loads); the next step's record and operands are loaded
-// while the current step's MFMAs issue.
-//
-// FP64: v_mfma_f64_4x4x4_4b_f64, the 4 blocks of one instruction are the 4
-//   column blocks t of the strip; A_{i,k} is replicated over them.
-// FP32: v_mfma_f32_4x4x1_16b_f32, the 16 blocks are (t, kk) pairs b = 4t + kk,
-//   each holding the rank-1 term of one inner index kk; the 4 partials are
-//   summed across lanes in the epilogue, after which lane l holds element l of
-//   the output strip.
-// ---------------------------------------------------------------------------
-template <class T> struct Mma;
-template <> struct Mma<double> {
-  typedef double acc_t;
-  static __device__ __forceinline__ acc_t zero() { return 0.0; }
-  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
-    return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
-  }
-};
-template <> struct Mma<float> {
-  typedef f4 acc_t;
-  static __device__ __forceinline__ acc_t zero() { return f4{0.f, 0.f, 0.f, 0.f}; }
-  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
-  }
-};
-
-// a step record lives in two lanes of a batch of 32 records (8 dwords per lane)
-__device__ __forceinline__ int rec_field(const int (&batch)[8], int r, int d) {
-  return __builtin_amdgcn_readlane(batch[d & 7], 2 * r + (d >> 3));
-}
-
-template <class T, bool TA>
-__global__ void __launch_bounds__(256) k_prod(const Tile* __restrict__ tiles, i64 ntiles,
-                                              const Step* __restrict__ steps, const T* __restrict__ A,
-                                              const T* __restrict__ B, T* __restrict__ C,
-                                              const uint8_t* __restrict__ cmask, T alpha, T beta) {
-  typedef typename Mma<T>::acc_t acc_t;
-  constexpr bool F64 = sizeof(T) == 8;
-  constexpr int RB = 32;   // step records per batch
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  // plain grid-stride over tiles (measured slightly faster than dealing
-  // contiguous tile chunks to the 8 XCDs)
-  const i64 t_begin = 0, t_end = ntiles, lb = blockIdx.x, nb_x = gridDim.x;
-  // FP64: lane = 16 kk + 4 blk + x.  FP32: lane = 16 t + 4 kk + x.
-  const int x = lane & 3;
-  const int kk = F64 ? (lane >> 4) : ((lane >> 2) & 3);
-  const int a_off = TA ? (kk * 4 + x) : (x * 4 + kk);
-  const int b_off = F64 ? (((lane >> 2) & 3) * 16 + (lane >> 4) * 4 + x) : lane;
-  const int* sw = reinterpret_cast<const int*>(steps);
-  for (i64 t = t_begin + lb * 4 + wave; t < t_end; t += nb_x * 4) {
-    const Tile* tp = tiles + uniform64(t);
-    const i64 s0 = tp->step0;
-    const int ns = tp->nsteps;
-    acc_t acc[4 * TJ];
-#pragma unroll
-    for (int q = 0; q < 4 * TJ; ++q) acc[q] = Mma<T>::zero();
-    if (ns > 0) {
-      // records of steps [s0 + RB*b, s0 + RB*(b+1)): lane l holds dwords 8l..8l+7
-      // (the step array is padded by one batch, so the last batch may overrun)
-      int cur[8], nxt[8];
-      {
-        const int* src = sw + (s0 * 16) + 8 * lane;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) cur[e] = src[e];
-      }
-      // operands of step 0
-      T av[4], bv[TJ];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const T* Ab = A + (i64)max(rec_field(cur, 0, i), 0) * 16;
-        av[i] = Ab[a_off];
-      }
-#pragma unroll
-      for (int j = 0; j < TJ; ++j) {
-        const T* Bb = B + (i64)max(rec_field(cur, 0, 4 + j), 0) * 64;
-        bv[j] = Bb[b_off];
-      }
-      uint32_t mask = (uint32_t)rec_field(cur, 0, 4 + TJ);
-      const int nbatch = (ns + RB - 1) / RB;
-      for (int b = 0; b < nbatch; ++b) {
-        {
-          const int* src = sw + (s0 + (i64)RB * (b + 1)) * 16 + 8 * lane;
-#pragma unroll
-          for (int e = 0; e < 8; ++e) nxt[e] = src[e];
-        }
-        const int rend = (ns - RB * b) < RB ? (ns - RB * b) : RB;
-        for (int r = 0; r < rend; ++r) {
-          // record of step s+1: in this batch, or the first of the next
-          int ra[4], rb[TJ];
-          uint32_t nmask;
-          if (r + 1 < RB) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) ra[i] = rec_field(cur, r + 1, i);
-#pragma unroll
-            for (int j = 0; j < TJ; ++j) rb[j] = rec_field(cur, r + 1, 4 + j);
-            nmask = (uint32_t)rec_field(cur, r + 1, 4 + TJ);
-          } else {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) ra[i] = rec_field(nxt, 0, i);
-#pragma unroll
-            for (int j = 0; j < TJ; ++j) rb[j] = rec_field(nxt, 0, 4 + j);
-            nmask = (uint32_t)rec_field(nxt, 0, 4 + TJ);
-          }
-          if (RB * b + r + 1 >= ns) nmask = 0u;
-          // operands of step s+1 (unconditional: absent operands read block 0,
-          // their slots are masked off)
-          T nav[4], nbv[TJ];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const T* Ab = A + (i64)max(ra[i], 0) * 16;
-            nav[i] = Ab[a_off];
-          }
-#pragma unroll
-          for (int j = 0; j < TJ; ++j) {
-            const T* Bb = B + (i64)max(rb[j], 0) * 64;
-            nbv[j] = Bb[b_off];
-          }
-          // MFMAs of step s
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < TJ; ++j)
-              if (mask >> (TJ * i + j) & 1u) acc[TJ * i + j] = Mma<T>::mma(av[i], bv[j], acc[TJ * i + j]);
-          mask = nmask;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) av[i] = nav[i];
-#pragma unroll
-          for (int j = 0; j < TJ; ++j) bv[j] = nbv[j];
-        }
-#pragma unroll
-        for (int e = 0; e < 8; ++e) cur[e] = nxt[e];
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 4 * TJ; ++q) {
-      const i32 cs = tp->cstrip[q];
-      if (cs < 0) continue;
-      T val;
-      int blk;
-      if constexpr (F64) {
-        val = acc[q];
-        blk = (lane >> 2) & 3;
-      } else {
-        f4 v = acc[q];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          v[e] += __shfl_xor(v[e], 4);
-          v[e] += __shfl_xor(v[e], 8);
-        }
-        val = kk == 0 ? v[0] : kk == 1 ? v[1] : kk == 2 ? v[2] : v[3];
-        blk = lane >> 4;
-      }
-      const bool keep = (cmask[cs] >> blk) & 1;
-      const i64 idx = (i64)cs * 64 + b_off;
-      T o = keep ? alpha * val : (T)0;
-      if (beta != (T)0) o += beta * C[idx];
-      C[idx] = o;
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// The same plans on the dense 16x16x4 MFMA: one instruction per active
-// column quad covers the 4 rows of the tile at once (rows without an A block
-// contribute zeros).  Fewer load and MFMA instructions per useful triple when
-// most rows of a step are active; more wasted lanes when few are.
+// Dense 16x16x4 MFMA forms used by the product kernels: one instruction per
+// active column quad covers the 4 rows of a row quad at once.
 //   f32 16x16x4: lane l holds A[l%16][l/16] and B[l/16][l%16]; D[4(l/16)+v][l%16]
 //   f64 16x16x4: same A and B; D[4v + l/16][l%16]          (measured on gfx950)
 // ---------------------------------------------------------------------------
@@ -268,126 +94,10 @@ template <> struct Mma16<float> {
   }
 };
 
-template <class T, bool TA>
-__global__ void __launch_bounds__(256) k_prod16(const Tile* __restrict__ tiles, i64 ntiles,
-                                                const Step* __restrict__ steps, const T* __restrict__ A,
-                                                const T* __restrict__ B, T* __restrict__ C,
-                                                const uint8_t* __restrict__ cmask, T alpha, T beta) {
-  typedef typename Mma16<T>::acc_t acc_t;
-  constexpr bool F64 = sizeof(T) == 8;
-  constexpr int RB = 32;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  // plain grid-stride over tiles (measured slightly faster than dealing
-  // contiguous tile chunks to the 8 XCDs)
-  const i64 t_begin = 0, t_end = ntiles, lb = blockIdx.x, nb_x = gridDim.x;
-  // A operand: row = l % 16 (tile row i = row / 4, block row r = row % 4), inner kk = l / 16
-  const int arow = lane & 15, ai = arow >> 2, ar = arow & 3, kk = lane >> 4;
-  const int a_off = TA ? (kk * 4 + ar) : (ar * 4 + kk);
-  // B operand: inner kk = l / 16, column = l % 16 (block t = col / 4, c = col % 4)
-  const int b_off = ((lane & 15) >> 2) * 16 + kk * 4 + (lane & 3);
-  const int* sw = reinterpret_cast<const int*>(steps);
-  for (i64 t = t_begin + lb * 4 + wave; t < t_end; t += nb_x * 4) {
-    const Tile* tp = tiles + uniform64(t);
-    const i64 s0 = tp->step0;
-    const int ns = tp->nsteps;
-    acc_t acc[TJ];
-#pragma unroll
-    for (int q = 0; q < TJ; ++q)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) acc[q][e] = (T)0;
-    if (ns > 0) {
-      int cur[8], nxt[8];
-      {
-        const int* src = sw + (s0 * 16) + 8 * lane;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) cur[e] = src[e];
-      }
-      auto a_load = [&](int a0, int a1, int a2, int a3) -> T {
-        const int a = ai == 0 ? a0 : ai == 1 ? a1 : ai == 2 ? a2 : a3;
-        const T v = A[(i64)max(a, 0) * 16 + a_off];
-        return a >= 0 ? v : (T)0;
-      };
-      T av = a_load(rec_field(cur, 0, 0), rec_field(cur, 0, 1), rec_field(cur, 0, 2), rec_field(cur, 0, 3));
-      T bv[TJ];
-#pragma unroll
-      for (int j = 0; j < TJ; ++j) bv[j] = B[(i64)max(rec_field(cur, 0, 4 + j), 0) * 64 + b_off];
-      uint32_t mask = (uint32_t)rec_field(cur, 0, 4 + TJ);
-      const int nbatch = (ns + RB - 1) / RB;
-      for (int b = 0; b < nbatch; ++b) {
-        {
-          const int* src = sw + (s0 + (i64)RB * (b + 1)) * 16 + 8 * lane;
-#pragma unroll
-          for (int e = 0; e < 8; ++e) nxt[e] = src[e];
-        }
-        const int rend = (ns - RB * b) < RB ? (ns - RB * b) : RB;
-        for (int r = 0; r < rend; ++r) {
-          int ra[4], rb[TJ];
-          uint32_t nmask;
-          if (r + 1 < RB) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) ra[i] = rec_field(cur, r + 1, i);
-#pragma unroll
-            for (int j = 0; j < TJ; ++j) rb[j] = rec_field(cur, r + 1, 4 + j);
-            nmask = (uint32_t)rec_field(cur, r + 1, 4 + TJ);
-          } else {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) ra[i] = rec_field(nxt, 0, i);
-#pragma unroll
-            for (int j = 0; j < TJ; ++j) rb[j] = rec_field(nxt, 0, 4 + j);
-            nmask = (uint32_t)rec_field(nxt, 0, 4 + TJ);
-          }
-          if (RB * b + r + 1 >= ns) nmask = 0u;
-          const T nav = a_load(ra[0], ra[1], ra[2], ra[3]);
-          T nbv[TJ];
-#pragma unroll
-          for (int j = 0; j < TJ; ++j) nbv[j] = B[(i64)max(rb[j], 0) * 64 + b_off];
-          // column quad jq is active when any row's slot (i, jq) is
-#pragma unroll
-          for (int j = 0; j < TJ; ++j) {
-            const uint32_t colbits = (mask >> j) & (1u | (1u << TJ) | (1u << (2 * TJ)) | (1u << (3 * TJ)));
-            if (colbits) acc[j] = Mma16<T>::mma(av, bv[j], acc[j]);
-          }
-          mask = nmask;
-          av = nav;
-#pragma unroll
-          for (int j = 0; j < TJ; ++j) bv[j] = nbv[j];
-        }
-#pragma unroll
-        for (int e = 0; e < 8; ++e) cur[e] = nxt[e];
-      }
-    }
-    // epilogue: lane l, register v holds D[row][col]; f32 row = 4 (l/16) + v,
-    // f64 row = 4 v + l/16; col = l % 16 (block t = col / 4, c = col % 4)
-    const int col = lane & 15, tb = col >> 2, cc = col & 3;
-#pragma unroll
-    for (int j = 0; j < TJ; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = F64 ? (4 * v + (lane >> 4)) : (4 * (lane >> 4) + v);
-        const int i = row >> 2, rr = row & 3;
-        const i32 c0 = tp->cstrip[j], c1 = tp->cstrip[TJ + j], c2 = tp->cstrip[2 * TJ + j], c3 = tp->cstrip[3 * TJ + j];
-        const i32 cs = i == 0 ? c0 : i == 1 ? c1 : i == 2 ? c2 : c3;
-        if (cs < 0) continue;
-        const bool keep = (cmask[cs] >> tb) & 1;
-        const i64 idx = (i64)cs * 64 + tb * 16 + rr * 4 + cc;
-        T o = keep ? alpha * acc[j][v] : (T)0;
-        if (beta != (T)0) o += beta * C[idx];
-        C[idx] = o;
-      }
-  }
-}
-
 // ---------------------------------------------------------------------------
-// BF16 products: v_mfma_f32_4x4x4_16b_bf16.  Lane l = 4b + x holds 4 bf16 of
-// A[b][x][0..3] (a row) and of B[b][0..3][x] (a column); D[b][r][c] is in lane
-// 4b + c, register r (measured on gfx950).  The 16 blocks of one instruction
-// are the 4 column quads of a group (g = l >> 4) times the 4 blocks of a strip
-// (t = (l >> 2) & 3), all against the same A_{i,k}, with the full inner
-// dimension 4 in one instruction.  Operand copies: A in row-major blocks ("R"),
-// or for a transposed A the column-major copy ("C") of X, whose column x of
-// X_{k,i} is row x of A_{i,k}; B always in column-major blocks.  FP32
-// accumulation, FP32 output strips (row-major) with alpha, beta.
+// BF16 operand copies: FP32 strips rounded to bf16 (nearest even), either in
+// the strip layout (row-major blocks, "R") or with every 4x4 block transposed
+// (column-major blocks, "C").
 // ---------------------------------------------------------------------------
 typedef short s4 __attribute__((ext_vector_type(4)));
 
@@ -410,205 +120,13 @@ __global__ void k_to_bf16(const float* __restrict__ in, unsigned short* __restri
   }
 }
 
-template <bool TA>
-__global__ void __launch_bounds__(256) k_prod_bf16(const Tile* __restrict__ tiles, i64 ntiles,
-                                                   const Step* __restrict__ steps,
-                                                   const unsigned short* __restrict__ A,
-                                                   const unsigned short* __restrict__ B, float* __restrict__ C,
-                                                   const uint8_t* __restrict__ cmask, float alpha, float beta) {
-  static_assert(TJ % 4 == 0, "column quads come in groups of 4");
-  constexpr int NG = TJ / 4;
-  constexpr int RB = 32;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  // plain grid-stride over tiles (measured slightly faster than dealing
-  // contiguous tile chunks to the 8 XCDs)
-  const i64 t_begin = 0, t_end = ntiles, lb = blockIdx.x, nb_x = gridDim.x;
-  const int x = lane & 3, tb = (lane >> 2) & 3, g = lane >> 4;
-  const int a_off = x * 4;             // row x of A_ik (R copy) = column x of X_ki (C copy)
-  const int b_off = tb * 16 + x * 4;   // column x of block tb (C copy)
-  const int* sw = reinterpret_cast<const int*>(steps);
-  for (i64 t = t_begin + lb * 4 + wave; t < t_end; t += nb_x * 4) {
-    const Tile* tp = tiles + uniform64(t);
-    const i64 s0 = tp->step0;
-    const int ns = tp->nsteps;
-    f4 acc[4 * NG];
-#pragma unroll
-    for (int q = 0; q < 4 * NG; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
-    if (ns > 0) {
-      int cur[8], nxt[8];
-      {
-        const int* src = sw + (s0 * 16) + 8 * lane;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) cur[e] = src[e];
-      }
-      s4 av[4], bv[NG];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        av[i] = *reinterpret_cast<const s4*>(A + (i64)max(rec_field(cur, 0, i), 0) * 16 + a_off);
-#pragma unroll
-      for (int q = 0; q < NG; ++q) {
-        const int b0 = rec_field(cur, 0, 4 + 4 * q), b1 = rec_field(cur, 0, 5 + 4 * q);
-        const int b2 = rec_field(cur, 0, 6 + 4 * q), b3 = rec_field(cur, 0, 7 + 4 * q);
-        const int bl = g == 0 ? b0 : g == 1 ? b1 : g == 2 ? b2 : b3;
-        // one instruction covers 4 column quads: an absent strip must be zeros
-        const s4 z = {0, 0, 0, 0};
-        const s4 ld = *reinterpret_cast<const s4*>(B + (i64)max(bl, 0) * 64 + b_off);
-        bv[q] = bl >= 0 ? ld : z;
-      }
-      uint32_t mask = (uint32_t)rec_field(cur, 0, 4 + TJ);
-      const int nbatch = (ns + RB - 1) / RB;
-      for (int b = 0; b < nbatch; ++b) {
-        {
-          const int* src = sw + (s0 + (i64)RB * (b + 1)) * 16 + 8 * lane;
-#pragma unroll
-          for (int e = 0; e < 8; ++e) nxt[e] = src[e];
-        }
-        const int rend = (ns - RB * b) < RB ? (ns - RB * b) : RB;
-        for (int r = 0; r < rend; ++r) {
-          int ra[4], rbl[NG];
-          uint32_t nmask;
-          if (r + 1 < RB) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) ra[i] = rec_field(cur, r + 1, i);
-#pragma unroll
-            for (int q = 0; q < NG; ++q) {
-              const int b0 = rec_field(cur, r + 1, 4 + 4 * q), b1 = rec_field(cur, r + 1, 5 + 4 * q);
-              const int b2 = rec_field(cur, r + 1, 6 + 4 * q), b3 = rec_field(cur, r + 1, 7 + 4 * q);
-              rbl[q] = g == 0 ? b0 : g == 1 ? b1 : g == 2 ? b2 : b3;
-            }
-            nmask = (uint32_t)rec_field(cur, r + 1, 4 + TJ);
-          } else {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) ra[i] = rec_field(nxt, 0, i);
-#pragma unroll
-            for (int q = 0; q < NG; ++q) {
-              const int b0 = rec_field(nxt, 0, 4 + 4 * q), b1 = rec_field(nxt, 0, 5 + 4 * q);
-              const int b2 = rec_field(nxt, 0, 6 + 4 * q), b3 = rec_field(nxt, 0, 7 + 4 * q);
-              rbl[q] = g == 0 ? b0 : g == 1 ? b1 : g == 2 ? b2 : b3;
-            }
-            nmask = (uint32_t)rec_field(nxt, 0, 4 + TJ);
-          }
-          if (RB * b + r + 1 >= ns) nmask = 0u;
-          s4 nav[4], nbv[NG];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) nav[i] = *reinterpret_cast<const s4*>(A + (i64)max(ra[i], 0) * 16 + a_off);
-#pragma unroll
-          for (int q = 0; q < NG; ++q) {
-            const s4 z = {0, 0, 0, 0};
-            const s4 ld = *reinterpret_cast<const s4*>(B + (i64)max(rbl[q], 0) * 64 + b_off);
-            nbv[q] = rbl[q] >= 0 ? ld : z;
-          }
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int q = 0; q < NG; ++q)
-              if ((mask >> (TJ * i + 4 * q)) & 15u)
-                acc[NG * i + q] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(av[i], bv[q], acc[NG * i + q], 0, 0, 0);
-          mask = nmask;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) av[i] = nav[i];
-#pragma unroll
-          for (int q = 0; q < NG; ++q) bv[q] = nbv[q];
-        }
-#pragma unroll
-        for (int e = 0; e < 8; ++e) cur[e] = nxt[e];
-      }
-    }
-    // lane 4(4g + tb) + x holds D[r][x] (r = 0..3) of output strip (i, 4q + g), block tb
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int q = 0; q < NG; ++q) {
-        const i32 c0 = tp->cstrip[TJ * i + 4 * q], c1 = tp->cstrip[TJ * i + 4 * q + 1];
-        const i32 c2 = tp->cstrip[TJ * i + 4 * q + 2], c3 = tp->cstrip[TJ * i + 4 * q + 3];
-        const i32 cs = g == 0 ? c0 : g == 1 ? c1 : g == 2 ? c2 : c3;
-        if (cs < 0) continue;
-        const bool keep = (cmask[cs] >> tb) & 1;
-        const f4 v = acc[NG * i + q];
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-          const i64 idx = (i64)cs * 64 + tb * 16 + rr * 4 + x;
-          float o = keep ? alpha * v[rr] : 0.f;
-          if (beta != 0.f) o += beta * C[idx];
-          C[idx] = o;
-        }
-      }
-  }
-}
-
 // ---------------------------------------------------------------------------
-// plan steps (symbolic pass, on the GPU): one wavefront per tile; lane
+// plan steps (symbolic pass, on the GPU): one wavefront per group tile; lane
 // (entry el, column jq) evaluates one inner entry against one output column
-// quad; the slot bits of an entry are OR-ed over its TJ lanes, active entries
+// quad; the slot bits of an entry are OR-ed over its GJ lanes, active entries
 // become steps in inner-list order.  Count pass: steps per tile and the useful
 // work (integer atomics, so the totals are exact and order independent).  Fill
 // pass: writes the step records from the tile's first step.
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_plan_steps(const Tile* __restrict__ tiles, i64 ntiles,
-                                                    const KEnt* __restrict__ kent, const i64* __restrict__ kbeg,
-                                                    PlanView v, int fill, i32* __restrict__ counts,
-                                                    Step* __restrict__ steps,
-                                                    unsigned long long* __restrict__ work) {
-  constexpr int EPI = 64 / TJ;   // inner entries per iteration
-  const int lane = threadIdx.x & 63;
-  const i64 wave0 = (i64)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const i64 nw = (i64)gridDim.x * 4;
-  const int jq = lane % TJ, el = lane / TJ;
-  for (i64 t = wave0; t < ntiles; t += nw) {
-    const Tile tl = tiles[t];
-    const i64 ck = tile_column_key(v, tl, jq);
-    const i64 kb = kbeg[tl.row_quad], ke = kbeg[tl.row_quad + 1];
-    i64 pos = tl.step0;
-    int cnt = 0;
-    uint64_t fl = 0, tr = 0;
-    for (i64 e0 = kb; e0 < ke; e0 += EPI) {
-      const i64 e = e0 + el;
-      i32 b = -1;
-      uint32_t bits = 0;
-      KEnt ent;
-      if (e < ke) {
-        ent = kent[e];
-        slot_work(v, tl, ent, jq, ck, &b, &bits, &fl, &tr);
-      }
-#pragma unroll
-      for (int o = 1; o < TJ; o <<= 1) bits |= (uint32_t)__shfl_xor((int)bits, o);
-      const bool active = bits != 0u;
-      const unsigned long long vote = __ballot(active && jq == 0);
-      if (fill && active) {
-        const int before = __popcll(vote & ((1ull << (el * TJ)) - 1ull));
-        int* sp = reinterpret_cast<int*>(steps + pos + before);
-        sp[4 + jq] = b;
-        if (jq == 0) {
-#pragma unroll
-          for (int ii = 0; ii < 4; ++ii) sp[ii] = ent.a[ii];
-          sp[4 + TJ] = (int)bits;
-#pragma unroll
-          for (int z = 5 + TJ; z < 16; ++z) sp[z] = 0;
-        }
-      }
-      const int nv = __popcll(vote);
-      pos += nv;
-      cnt += nv;
-    }
-    if (!fill) {
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        fl += (uint64_t)__shfl_xor((long long)fl, o);
-        tr += (uint64_t)__shfl_xor((long long)tr, o);
-      }
-      if (lane == 0) {
-        counts[t] = cnt;
-        atomicAdd(work, (unsigned long long)fl);
-        atomicAdd(work + 1, (unsigned long long)tr);
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// group plan steps: as k_plan_steps, for group tiles (GQ row quads sharing one
-// inner list); one wavefront per tile, lane (entry el, column jq)
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_plan_gsteps(const GTile* __restrict__ tiles, i64 ntiles,
                                                      const GKEnt* __restrict__ kent, const i64* __restrict__ kbeg,
@@ -643,6 +161,7 @@ __global__ void __launch_bounds__(256) k_plan_gsteps(const GTile* __restrict__ t
       }
       const bool active = any != 0u;
       const unsigned long long vote = __ballot(active && jq == 0);
+      const unsigned long long bvote = __ballot(b >= 0);
       if (fill && active) {
         const int before = __popcll(vote & ((1ull << (el * GJ)) - 1ull));
         int* sp = reinterpret_cast<int*>(steps + pos + before);
@@ -658,8 +177,9 @@ __global__ void __launch_bounds__(256) k_plan_gsteps(const GTile* __restrict__ t
 #pragma unroll
           for (int w = 0; w < GQ; ++w) sp[GROWS + GJ + w] = (int)m[w];
           sp[GROWS + GJ + GQ] = (int)rows;
+          sp[GROWS + GJ + GQ + 1] = (int)((bvote >> (el * GJ)) & ((1ull << GJ) - 1ull));
 #pragma unroll
-          for (int z = GROWS + GJ + GQ + 1; z < 32; ++z) sp[z] = 0;
+          for (int z = GROWS + GJ + GQ + 2; z < 32; ++z) sp[z] = 0;
         }
       }
       const int nv = __popcll(vote);
@@ -699,7 +219,9 @@ __global__ void __launch_bounds__(256) k_plan_gsteps(const GTile* __restrict__ t
 // Rows without an A block are zeroed when the operand is read from LDS; a
 // column whose B strip is absent has no active slot and issues no MFMA.
 // ---------------------------------------------------------------------------
-// steps per staged batch (LDS: 2 x SB steps of A and B operands)
+// Steps per staged batch (LDS: 2 x SB steps of A and B operands).  Measured
+// on the 32768-atom RL16 chain: smaller batches with more resident
+// workgroups beat larger batches or a second batch of loads in flight.
 #ifndef LSDM_GSB_F32
 #define LSDM_GSB_F32 4
 #endif
@@ -785,11 +307,7 @@ __global__ void __launch_bounds__(256) k_gprod(const GTile* __restrict__ tiles, 
         const int off = part * PV + lane * VPL;
         const T* src = part * PV < AV ? A + (i64)max(idx[i], 0) * 16 + (off & 15)
                                       : B + (i64)max(idx[i], 0) * 64 + ((off - AV) & 63);
-#ifdef LSDM_GNT
-        d[i] = __builtin_nontemporal_load(reinterpret_cast<const i4v*>(src));
-#else
         d[i] = *reinterpret_cast<const i4v*>(src);
-#endif
       }
     };
     auto store_operands = [&](const i4v (&d)[NPW], int dslot) {
@@ -876,6 +394,170 @@ __global__ void __launch_bounds__(256) k_gprod(const GTile* __restrict__ tiles, 
         }
     }
     // the next tile's prologue reuses record slots 0, 1 and operand slot 0
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// BF16 group-tile product: the staging of k_gprod with bf16 operands (8 bytes
+// per lane per piece) and v_mfma_f32_16x16x16_bf16, one instruction per
+// active column quad covering 4 consecutive steps: lane l holds A[l%16][4g..4g+3]
+// and B[4g..4g+3][l%16] for step slice g = l/16, i.e. one row of A_{r,k} (a
+// column of X_{k,r} for a transposed A, from the column-major copy) and one
+// column of a B block (column-major copy); D[4(l/16)+v][l%16] as for FP32.
+// A slice is zeroed where its step lies past the tile's end, its row has no
+// A block, or (for B) its column quad has no B strip.
+// ---------------------------------------------------------------------------
+typedef int i2v __attribute__((ext_vector_type(2)));
+
+template <bool TA>
+__global__ void __launch_bounds__(256) k_gprod_bf16(const GTile* __restrict__ tiles, i64 ntiles,
+                                                    const GStep* __restrict__ steps,
+                                                    const unsigned short* __restrict__ A,
+                                                    const unsigned short* __restrict__ B, float* __restrict__ C,
+                                                    const uint8_t* __restrict__ cmask, float alpha, float beta) {
+  constexpr int SB = 8;                 // steps per batch: two MFMA groups of KG steps
+  constexpr int KG = 4;
+  constexpr int AV = GROWS * 16;
+  constexpr int BV = GJ * 64;
+  constexpr int SV = AV + BV;
+  constexpr int VPL = 4;                // bf16 values per lane of one piece (8 bytes)
+  constexpr int PV = 64 * VPL;
+  constexpr int PPS = SV / PV;
+  constexpr int SPW = SB / GQ;
+  constexpr int NPW = SPW * PPS;
+  constexpr int RW = 32;
+  constexpr int RLANES = SB * RW / 4;
+  static_assert(AV % PV == 0 && BV % PV == 0 && SB % GQ == 0 && SB % KG == 0 && RLANES <= 64, "staging layout");
+  __shared__ __attribute__((aligned(16))) unsigned short dbuf[2][SB * SV];
+  __shared__ __attribute__((aligned(16))) int rbuf[3][SB * RW];
+  __shared__ int2 cinfo[GQ][4 * GJ];
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int arow = lane & 15, ai = arow >> 2, ar = arow & 3, ks = lane >> 4;
+  const int a_off = (4 * wave + ai) * 16 + ar * 4;
+  const int b_off = ((lane & 15) >> 2) * 16 + (lane & 3) * 4;
+  const int abit = 4 * wave + ai;
+  constexpr uint32_t COL = 1u | (1u << GJ) | (1u << (2 * GJ)) | (1u << (3 * GJ));
+  const i64 xcd = blockIdx.x & 7, nbx = gridDim.x >> 3, lb = blockIdx.x >> 3;
+  const i64 t_begin = ntiles * xcd / 8, t_end = ntiles * (xcd + 1) / 8;
+  const i4v* recs = reinterpret_cast<const i4v*>(steps);
+
+  for (i64 t = t_begin + lb; t < t_end; t += nbx) {
+    const GTile* tp = tiles + uniform64(t);
+    const i64 s0 = tp->step0;
+    const int ns = tp->nsteps;
+    f4 acc[GJ];
+#pragma unroll
+    for (int q = 0; q < GJ; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[q][e] = 0.f;
+    const int nb = (ns + SB - 1) / SB;
+    auto load_records = [&](int q) -> i4v {
+      i4v v = {0, 0, 0, 0};
+      if (wave == 0 && lane < RLANES) v = recs[(s0 + (i64)SB * q) * (RW / 4) + lane];
+      return v;
+    };
+    auto store_records = [&](const i4v& v, int slot) {
+      if (wave == 0 && lane < RLANES) *reinterpret_cast<i4v*>(&rbuf[slot][4 * lane]) = v;
+    };
+    auto load_operands = [&](int rslot, i2v (&d)[NPW]) {
+      int idx[NPW];
+#pragma unroll
+      for (int i = 0; i < NPW; ++i) {
+        const int r = SPW * wave + i / PPS, part = i % PPS;
+        const int off = part * PV + lane * VPL;
+        idx[i] = part * PV < AV ? rbuf[rslot][r * RW + (off >> 4)] : rbuf[rslot][r * RW + GROWS + ((off - AV) >> 6)];
+      }
+#pragma unroll
+      for (int i = 0; i < NPW; ++i) {
+        const int part = i % PPS;
+        const int off = part * PV + lane * VPL;
+        const unsigned short* src = part * PV < AV ? A + (i64)max(idx[i], 0) * 16 + (off & 15)
+                                                   : B + (i64)max(idx[i], 0) * 64 + ((off - AV) & 63);
+        d[i] = *reinterpret_cast<const i2v*>(src);
+      }
+    };
+    auto store_operands = [&](const i2v (&d)[NPW], int dslot) {
+#pragma unroll
+      for (int i = 0; i < NPW; ++i) {
+        const int r = SPW * wave + i / PPS, part = i % PPS;
+        *reinterpret_cast<i2v*>(&dbuf[dslot][r * SV + part * PV + lane * VPL]) = d[i];
+      }
+    };
+    const i32 my_cs = lane < 4 * GJ ? tp->cstrip[4 * GJ * wave + lane] : -1;
+    if (nb > 0) {
+      {
+        const i4v r0 = load_records(0);
+        const i4v r1 = nb > 1 ? load_records(1) : i4v{0, 0, 0, 0};
+        store_records(r0, 0);
+        store_records(r1, 1);
+      }
+      __syncthreads();
+      {
+        i2v d[NPW];
+        load_operands(0, d);
+        const int mk = my_cs >= 0 ? (int)cmask[my_cs] : 0;
+        store_operands(d, 0);
+        if (lane < 4 * GJ) cinfo[wave][lane] = int2{my_cs, mk};
+      }
+    } else if (lane < 4 * GJ) {
+      cinfo[wave][lane] = int2{my_cs, my_cs >= 0 ? (int)cmask[my_cs] : 0};
+    }
+    for (int q = 0; q < nb; ++q) {
+      __syncthreads();
+      const bool more_r = q + 2 < nb, more_d = q + 1 < nb;
+      i4v rn = {0, 0, 0, 0};
+      i2v dn[NPW];
+      if (more_r) rn = load_records(q + 2);
+      if (more_d) load_operands((q + 1) % 3, dn);
+      const int rs = q % 3, ds = q & 1;
+      const int nv = ns - SB * q;
+#pragma unroll 1
+      for (int g = 0; g < SB / KG; ++g) {
+        const int rl = KG * g + ks;                      // this lane's step in the batch
+        const int* rec = &rbuf[rs][rl * RW];
+        const bool valid = rl < nv;
+        const uint32_t m_l = valid ? (uint32_t)rec[GROWS + GJ + wave] : 0u;
+        const uint32_t rows_l = (uint32_t)rec[GROWS + GJ + GQ];
+        const uint32_t bcols_l = (uint32_t)rec[GROWS + GJ + GQ + 1];
+        const uint32_t colany = (uint32_t)__builtin_amdgcn_readlane((int)m_l, 0) |
+                                (uint32_t)__builtin_amdgcn_readlane((int)m_l, 16) |
+                                (uint32_t)__builtin_amdgcn_readlane((int)m_l, 32) |
+                                (uint32_t)__builtin_amdgcn_readlane((int)m_l, 48);
+        if (colany == 0u) continue;
+        const unsigned short* sS = &dbuf[ds][rl * SV];
+        s4 av = *reinterpret_cast<const s4*>(sS + a_off);
+        if (!(valid && ((rows_l >> abit) & 1u))) av = s4{0, 0, 0, 0};
+        s4 bv[GJ];
+#pragma unroll
+        for (int j = 0; j < GJ; ++j) {
+          bv[j] = *reinterpret_cast<const s4*>(sS + AV + j * 64 + b_off);
+          if (!((bcols_l >> j) & 1u)) bv[j] = s4{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int j = 0; j < GJ; ++j)
+          if ((colany >> j) & COL) acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv[j], acc[j], 0, 0, 0);
+      }
+      if (more_d) store_operands(dn, (q + 1) & 1);
+      if (more_r) store_records(rn, (q + 2) % 3);
+    }
+    {
+      const int col = lane & 15, tb = col >> 2, cc = col & 3;
+#pragma unroll
+      for (int j = 0; j < GJ; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = lane >> 4, rr = v;
+          const int2 ci = cinfo[wave][GJ * i + j];
+          if (ci.x < 0) continue;
+          const i64 idx = (i64)ci.x * 64 + tb * 16 + rr * 4 + cc;
+          float o = ((ci.y >> tb) & 1) ? alpha * acc[j][v] : 0.f;
+          if (beta != 0.f) o += beta * C[idx];
+          C[idx] = o;
+        }
+    }
     __syncthreads();
   }
 }
@@ -1109,23 +791,6 @@ void transpose_strips(const lsdm_pattern* p, const T* in, T* out, hipStream_t st
 template void transpose_strips<double>(const lsdm_pattern*, const double*, double*, hipStream_t);
 template void transpose_strips<float>(const lsdm_pattern*, const float*, float*, hipStream_t);
 
-// Grid of the product kernels: up to 16384 workgroups of 4 wavefronts, one
-// tile per wavefront at a time (grid-stride).
-unsigned product_grid(i64 ntiles) {
-  i64 blocks = (ntiles + 3) / 4;
-  if (blocks > 16384) blocks = 16384;
-  blocks = (blocks + 7) / 8 * 8;
-  if (blocks < 8) blocks = 8;
-  return (unsigned)blocks;
-}
-
-// which product kernel runs for FP64/FP32: the dense 16x16x4 form (k_prod16,
-// measured 1.2x (FP64) and 2.5x (FP32) faster on the RL16 chain) or the
-// 4x4-block form (k_prod, fewer wasted lanes, more load instructions)
-static bool dense_product_kernel() { return true; }
-// the LDS-staged group-tile kernel (k_gprod) for FP64/FP32
-static bool group_product_kernel() { return true; }
-
 // Grid of the group kernel: as many workgroups as are resident at once (so
 // every workgroup of an XCD walks its tile range in step with the others), a
 // multiple of 8 (one contiguous tile range per XCD).
@@ -1154,47 +819,21 @@ static unsigned gproduct_grid(K kernel, i64 ntiles) {
 
 template <class T>
 void product(const lsdm_plan* pl, const T* A, const T* B, T* C, double alpha, double beta, hipStream_t st) {
+  if (pl->n_gtiles == 0) return;
   const uint8_t* cm = pl->C->d_smask.as<uint8_t>();
-  if (group_product_kernel()) {
-    if (pl->n_gtiles == 0) return;
-    const GTile* Tl = pl->d_gtiles.as<GTile>();
-    const GStep* S = pl->d_gsteps.as<GStep>();
-    const dim3 b(256);
-    if (pl->transA)
-      hipLaunchKernelGGL((k_gprod<T, true>), dim3(gproduct_grid(k_gprod<T, true>, pl->n_gtiles)), b, 0, st, Tl,
-                         pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta);
-    else
-      hipLaunchKernelGGL((k_gprod<T, false>), dim3(gproduct_grid(k_gprod<T, false>, pl->n_gtiles)), b, 0, st, Tl,
-                         pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta);
-    return;
-  }
-  if (pl->n_tiles == 0) return;
-  const Tile* Tl = pl->d_tiles.as<Tile>();
-  const Step* S = pl->d_steps.as<Step>();
-  const dim3 g(product_grid(pl->n_tiles)), b(256);
-  if (dense_product_kernel()) {
-    if (pl->transA)
-      hipLaunchKernelGGL((k_prod16<T, true>), g, b, 0, st, Tl, pl->n_tiles, S, A, B, C, cm, (T)alpha, (T)beta);
-    else
-      hipLaunchKernelGGL((k_prod16<T, false>), g, b, 0, st, Tl, pl->n_tiles, S, A, B, C, cm, (T)alpha, (T)beta);
-    return;
-  }
+  const GTile* Tl = pl->d_gtiles.as<GTile>();
+  const GStep* S = pl->d_gsteps.as<GStep>();
+  const dim3 b(256);
   if (pl->transA)
-    hipLaunchKernelGGL((k_prod<T, true>), g, b, 0, st, Tl, pl->n_tiles, S, A, B, C, cm, (T)alpha, (T)beta);
+    hipLaunchKernelGGL((k_gprod<T, true>), dim3(gproduct_grid(k_gprod<T, true>, pl->n_gtiles)), b, 0, st, Tl,
+                       pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta);
   else
-    hipLaunchKernelGGL((k_prod<T, false>), g, b, 0, st, Tl, pl->n_tiles, S, A, B, C, cm, (T)alpha, (T)beta);
+    hipLaunchKernelGGL((k_gprod<T, false>), dim3(gproduct_grid(k_gprod<T, false>, pl->n_gtiles)), b, 0, st, Tl,
+                       pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta);
 }
 template void product<double>(const lsdm_plan*, const double*, const double*, double*, double, double, hipStream_t);
 template void product<float>(const lsdm_plan*, const float*, const float*, float*, double, double, hipStream_t);
 
-void plan_steps(const Tile* tiles, i64 ntiles, const KEnt* kent, const i64* kbeg, const PlanView& v, int fill,
-                i32* counts, Step* steps, unsigned long long* work) {
-  if (ntiles == 0) return;
-  i64 blocks = (ntiles + 3) / 4;
-  if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(k_plan_steps, dim3((unsigned)blocks), dim3(256), 0, 0, tiles, ntiles, kent, kbeg, v, fill, counts,
-                     steps, work);
-}
 
 void plan_gsteps(const GTile* tiles, i64 ntiles, const GKEnt* kent, const i64* kbeg, const PlanView& v, int fill,
                  i32* counts, GStep* steps, unsigned long long* work) {
@@ -1238,15 +877,17 @@ void to_bf16(const float* in, unsigned short* outR, unsigned short* outC, i64 n,
 
 void product_bf16(const lsdm_plan* pl, const unsigned short* A, const unsigned short* B, float* C, double alpha,
                   double beta, hipStream_t st) {
-  if (pl->n_tiles == 0) return;
-  const Tile* Tl = pl->d_tiles.as<Tile>();
-  const Step* S = pl->d_steps.as<Step>();
+  if (pl->n_gtiles == 0) return;
+  const GTile* Tl = pl->d_gtiles.as<GTile>();
+  const GStep* S = pl->d_gsteps.as<GStep>();
   const uint8_t* cm = pl->C->d_smask.as<uint8_t>();
-  const dim3 g(product_grid(pl->n_tiles)), b(256);
+  const dim3 b(256);
   if (pl->transA)
-    hipLaunchKernelGGL((k_prod_bf16<true>), g, b, 0, st, Tl, pl->n_tiles, S, A, B, C, cm, (float)alpha, (float)beta);
+    hipLaunchKernelGGL((k_gprod_bf16<true>), dim3(gproduct_grid(k_gprod_bf16<true>, pl->n_gtiles)), b, 0, st, Tl,
+                       pl->n_gtiles, S, A, B, C, cm, (float)alpha, (float)beta);
   else
-    hipLaunchKernelGGL((k_prod_bf16<false>), g, b, 0, st, Tl, pl->n_tiles, S, A, B, C, cm, (float)alpha, (float)beta);
+    hipLaunchKernelGGL((k_gprod_bf16<false>), dim3(gproduct_grid(k_gprod_bf16<false>, pl->n_gtiles)), b, 0, st, Tl,
+                       pl->n_gtiles, S, A, B, C, cm, (float)alpha, (float)beta);
 }
 
 template <class T>

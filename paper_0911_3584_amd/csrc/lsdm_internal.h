@@ -126,33 +126,7 @@ struct lsdm_pattern {
 
 namespace lsdm {
 
-// Tile width in column quads: one wavefront accumulates 4 output rows x TJ
-// column quads (4 * TJ slots of 4 blocks each).
-constexpr int TJ = 8;
-
-// One output tile of a product: a quad of 4 output rows x up to TJ column quads.
-struct Tile {
-  i32 row_quad;
-  i32 nsteps;
-  i64 step0;
-  i32 cstrip[4 * TJ];   // output strip of slot (i, jq) = [TJ*i + jq], -1 if absent
-};
-
-// One step of a tile: a k pseudo-atom (with image) and its operands.  64 bytes,
-// read with one scalar load.
-//   a[i]: strip-layout offset / 16 of the 4x4 block A_{i,k} (or of X_{k,i} for a
-//         transposed A), -1 if absent
-//   b[jq]: strip index of B's strip (k, quad jq), -1 if absent
-//   mask: bit TJ*i + jq set when slot (i, jq) has at least one useful triple
-struct alignas(64) Step {
-  i32 a[4];
-  i32 b[TJ];
-  uint32_t mask;
-  i32 pad[3];
-};
-static_assert(sizeof(Step) == 64, "step record is one 64-byte scalar load");
-
-// Group tiles (the FP64/FP32 products): a workgroup of GQ wavefronts computes
+// Group tiles of the product kernels: a workgroup of GQ wavefronts computes
 // GQ consecutive row quads (4 * GQ output rows, one quad per wavefront) x GJ
 // column quads over one shared step list, the union of the rows' inner
 // entries, so every B strip of a step is fetched once for all GQ row quads.
@@ -174,12 +148,14 @@ struct GTile {
 //   b[jq]: strip index of B's strip (k, quad jq), -1 if absent
 //   mask[w]: slots of wavefront w, bit GJ*i + jq for row 4w+i
 //   rows: bit r set when a[r] >= 0
+//   bcols: bit jq set when b[jq] >= 0
 struct alignas(128) GStep {
   i32 a[GROWS];
   i32 b[GJ];
   uint32_t mask[GQ];
   uint32_t rows;
-  i32 pad[3];
+  uint32_t bcols;
+  i32 pad[2];
 };
 static_assert(sizeof(GStep) == 128, "group step record is 128 bytes");
 static_assert(4 * GJ <= 32, "a wavefront's slots fit one 32-bit mask");
@@ -191,9 +167,8 @@ struct lsdm_plan {
   const lsdm_pattern* B = nullptr;
   const lsdm_pattern* C = nullptr;
   int transA = 0, transB = 0;
-  lsdm::i64 n_tiles = 0, n_steps = 0, n_triples = 0;
+  lsdm::i64 n_triples = 0;
   double flops = 0;
-  lsdm::DevBuf d_tiles, d_steps;
   // group tiles and their steps
   lsdm::i64 n_gtiles = 0, n_gsteps = 0;
   lsdm::DevBuf d_gtiles, d_gsteps;

@@ -1,22 +1,15 @@
 // Step generation of a product plan, shared by the GPU kernel (kernels.hip)
 // and the host path used when no device is present (symbolic.cpp).
 //
-// For a tile (4 output rows of a row quad x TJ output column quads) and one
-// entry of the row quad's inner list (pseudo-atom k with image m, and the A
-// blocks of the 4 rows), the B strip reaching column quad jq is (k, Q_jq,
-// n_jq - m); slot (i, jq) is active when A_{i,k} exists and the strip holds a
-// block (k, j) whose pair (i, j) is in C's pattern.
+// For a group tile (4*GQ output rows x GJ output column quads) and one entry
+// of the group's inner list (pseudo-atom k with image m, and the A blocks of
+// the rows), the B strip reaching column quad jq is (k, Q_jq, n_jq - m); slot
+// (r, jq) is active when A_{r,k} exists and the strip holds a block (k, j)
+// whose pair (r, j) is in C's pattern.
 #pragma once
 #include "lsdm_internal.h"
 
 namespace lsdm {
-
-// one entry of a row quad's inner list
-struct KEnt {
-  i32 k;
-  i32 m;      // packed image of k
-  i32 a[4];   // A block index (strip layout offset / 16) per row, -1 if absent
-};
 
 // read-only views used by step generation
 struct PlanView {
@@ -43,44 +36,6 @@ __host__ __device__ inline i64 find_b_strip(const PlanView& v, i32 k, i64 key) {
   }
   if (lo < v.b_sptr[k + 1] && skey(v.b_squad[lo], v.b_simg[lo]) == key) return lo;
   return -1;
-}
-
-// Column key of column jq of a tile (from any row's output strip), or -1.
-__host__ __device__ inline i64 tile_column_key(const PlanView& v, const Tile& t, int jq) {
-  for (int ii = 0; ii < 4; ++ii) {
-    const i32 cs = t.cstrip[TJ * ii + jq];
-    if (cs >= 0) return skey(v.c_squad[cs], v.c_simg[cs]);
-  }
-  return -1;
-}
-
-// Work of one (tile, inner entry, column quad): B strip index, slot bits
-// (bit TJ*i + jq), useful flops and atom triples.
-__host__ __device__ inline void slot_work(const PlanView& v, const Tile& t, const KEnt& e, int jq, i64 colkey,
-                                          i32* bidx, uint32_t* bits, uint64_t* flops, uint64_t* triples) {
-  *bidx = -1;
-  *bits = 0;
-  if (colkey < 0) return;
-  const i32 q = (i32)(colkey >> 24), n = (i32)(colkey & 0xffffff);
-  const i64 b = find_b_strip(v, e.k, skey(q, img_sub(n, e.m)));
-  if (b < 0) return;
-  *bidx = (i32)b;
-  const uint8_t bm = v.b_smask[b];
-  for (int ii = 0; ii < 4; ++ii) {
-    if (e.a[ii] < 0) continue;
-    const i32 cs = t.cstrip[TJ * ii + jq];
-    if (cs < 0) continue;
-    const uint8_t u = bm & v.c_smask[cs];
-    if (!u) continue;
-    *bits |= 1u << (TJ * ii + jq);
-    const i32 pi = 4 * t.row_quad + ii;
-    for (int bb = 0; bb < 4; ++bb) {
-      if (!(u >> bb & 1)) continue;
-      const i32 pj = 4 * q + bb;
-      *flops += 2ull * (uint64_t)v.prows[pi] * (uint64_t)v.prows[e.k] * (uint64_t)v.prows[pj];
-      if (v.first[pi] && v.first[e.k] && v.first[pj]) *triples += 1;
-    }
-  }
 }
 
 // ---------------------------------------------------------------------------
