@@ -567,8 +567,8 @@ __global__ void __launch_bounds__(256) k_gprod_bf16(const GTile* __restrict__ ti
 // (a, a, 0); with pseudo-atoms, every pair of pseudo-atoms of one atom) and
 // the rest R: AB = R_A R_B + D_A B + A D_B - D_A D_B.  R_A R_B runs on the FP32
 // product kernel; the other three terms are block-diagonal scalings done here
-// in FP64, one thread per output block, finding the blocks it needs by binary
-// search in the strip lists.
+// in FP64.  The blocks each output block needs are found once per plan (binary
+// search in the strip lists) and kept as index maps.
 // ---------------------------------------------------------------------------
 struct PatDev {
   const i64* sptr;
@@ -603,59 +603,93 @@ __global__ void k_offsite_f32(const double* __restrict__ in, float* __restrict__
   }
 }
 
+// op(A)_{p,(x,m)}: A's block (p, x, m), or for a transposed A the transpose
+// of A's block (x, p, -m); value offset or -1
 template <bool TA>
-__global__ void k_rc_correct(PatDev A, PatDev B, PatDev C, const i32* __restrict__ srow,
-                             const double* __restrict__ A64, const double* __restrict__ B64,
-                             const float* __restrict__ RR, double* __restrict__ C64, const i32* __restrict__ patom,
-                             const i32* __restrict__ pbase, const i32* __restrict__ npseudo, i64 ncstrips,
-                             double alpha, double beta) {
-  // op(A)_{p,(x,m)}: A's block (p, x, m), or the transpose of A's block (x, p, -m)
-  auto opa = [&](i32 p, i32 x, i32 m) -> i64 { return TA ? block_off(A, x, p, img_neg(m)) : block_off(A, p, x, m); };
+__device__ __forceinline__ i64 opa_off(const PatDev& A, i32 p, i32 x, i32 m) {
+  return TA ? block_off(A, x, p, img_neg(m)) : block_off(A, p, x, m);
+}
+__device__ __forceinline__ i32 blk_index(i64 off) { return off < 0 ? -1 : (i32)(off >> 4); }
+
+// residual-mode maps of a plan, one thread per output block (see lsdm_plan)
+template <bool TA>
+__global__ void k_rc_map(PatDev A, PatDev B, PatDev C, const i32* __restrict__ srow, const i32* __restrict__ patom,
+                         const i32* __restrict__ pbase, const i32* __restrict__ npseudo, int np, i64 ncstrips,
+                         i32* __restrict__ bmap, i32* __restrict__ amap) {
   for (i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x; g < ncstrips * 4; g += (i64)gridDim.x * blockDim.x) {
     const i64 st = g >> 2;
     const int t = (int)(g & 3);
-    const i64 base = st * 64 + t * 16;
-    double acc[16];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) acc[e] = 0.0;
-    const bool in = (C.smask[st] >> t) & 1;
     const i32 p = srow[st], q = 4 * C.squad[st] + t, n = C.simg[st];
-    auto add = [&](i64 a, i64 b, double sgn) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          double v = 0.0;
-#pragma unroll
-          for (int k = 0; k < 4; ++k) v += (TA ? A64[a + k * 4 + r] : A64[a + r * 4 + k]) * B64[b + k * 4 + c];
-          acc[r * 4 + c] += sgn * v;
-        }
-    };
+    const i32 ap = patom[p], aq = patom[q];
+    for (int u = 0; u < np; ++u) {
+      i64 b = -1, a = -1;
+      if (ap >= 0 && u < npseudo[ap]) b = block_off(B, pbase[ap] + u, q, n);
+      if (aq >= 0 && u < npseudo[aq]) a = opa_off<TA>(A, p, pbase[aq] + u, n);
+      bmap[g * np + u] = blk_index(b);
+      amap[g * np + u] = blk_index(a);
+    }
+  }
+}
+template <bool TA>
+__global__ void k_rc_onsite(PatDev A, PatDev B, const i32* __restrict__ patom, const i32* __restrict__ pbase,
+                            const i32* __restrict__ npseudo, int np, i32 n_pseudo, i32* __restrict__ aon,
+                            i32* __restrict__ bon) {
+  for (i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x; g < (i64)n_pseudo * np; g += (i64)gridDim.x * blockDim.x) {
+    const i32 p = (i32)(g / np);
+    const int u = (int)(g % np);
+    const i32 ap = patom[p];
+    i64 a = -1, b = -1;
+    if (ap >= 0 && u < npseudo[ap]) {
+      a = opa_off<TA>(A, p, pbase[ap] + u, IMG0);
+      b = block_off(B, pbase[ap] + u, p, IMG0);
+    }
+    aon[g] = blk_index(a);
+    bon[g] = blk_index(b);
+  }
+}
+
+// C = alpha (RR + D_A B + A D_B - D_A D_B) + beta C in FP64, one thread per
+// output element (16 per block), the blocks it needs read from the maps
+template <bool TA>
+__global__ void k_rc_apply(const uint8_t* __restrict__ cmask, const i32* __restrict__ srow,
+                           const i32* __restrict__ csquad, const i32* __restrict__ csimg,
+                           const i32* __restrict__ patom, int np, const i32* __restrict__ bmap,
+                           const i32* __restrict__ amap, const i32* __restrict__ aon, const i32* __restrict__ bon,
+                           const double* __restrict__ A64, const double* __restrict__ B64,
+                           const float* __restrict__ RR, double* __restrict__ C64, i64 ncstrips, double alpha,
+                           double beta) {
+  for (i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x; g < ncstrips * 64; g += (i64)gridDim.x * blockDim.x) {
+    const i64 st = g >> 6, blk = g >> 4;
+    const int t = (int)((g >> 4) & 3), e = (int)(g & 15), r = e >> 2, c = e & 3;
+    const bool in = (cmask[st] >> t) & 1;
+    double acc = 0.0;
     if (in) {
-      const i32 ap = patom[p], aq = patom[q];
-      // D_A B: the on-site blocks of row p times B's blocks (p', q, n)
-      for (i32 pp = pbase[ap]; pp < pbase[ap] + npseudo[ap]; ++pp) {
-        const i64 a = opa(p, pp, IMG0), b = block_off(B, pp, q, n);
-        if (a >= 0 && b >= 0) add(a, b, 1.0);
+      const i32 p = srow[st], q = 4 * csquad[st] + t, n = csimg[st];
+      auto prod = [&](i32 a, i32 b) -> double {
+        const double* Ab = A64 + (i64)a * 16;
+        const double* Bb = B64 + (i64)b * 16;
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v += (TA ? Ab[k * 4 + r] : Ab[r * 4 + k]) * Bb[k * 4 + c];
+        return v;
+      };
+      for (int u = 0; u < np; ++u) {   // D_A B
+        const i32 a = aon[(i64)p * np + u], b = bmap[blk * np + u];
+        if (a >= 0 && b >= 0) acc += prod(a, b);
       }
-      // A D_B: op(A)'s blocks (p, q', n) times the on-site blocks of column q
-      for (i32 qq = pbase[aq]; qq < pbase[aq] + npseudo[aq]; ++qq) {
-        const i64 a = opa(p, qq, n), b = block_off(B, qq, q, IMG0);
-        if (a >= 0 && b >= 0) add(a, b, 1.0);
+      for (int u = 0; u < np; ++u) {   // A D_B
+        const i32 a = amap[blk * np + u], b = bon[(i64)q * np + u];
+        if (a >= 0 && b >= 0) acc += prod(a, b);
       }
-      // - D_A D_B (counted in both terms above)
-      if (ap == aq && n == IMG0)
-        for (i32 pp = pbase[ap]; pp < pbase[ap] + npseudo[ap]; ++pp) {
-          const i64 a = opa(p, pp, IMG0), b = block_off(B, pp, q, IMG0);
-          if (a >= 0 && b >= 0) add(a, b, -1.0);
+      if (n == IMG0 && patom[p] >= 0 && patom[p] == patom[q])
+        for (int u = 0; u < np; ++u) {   // - D_A D_B (counted in both terms above)
+          const i32 a = aon[(i64)p * np + u], b = bon[(i64)q * np + u];
+          if (a >= 0 && b >= 0) acc -= prod(a, b);
         }
     }
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      double o = in ? alpha * ((double)RR[base + e] + acc[e]) : 0.0;
-      if (beta != 0.0) o += beta * C64[base + e];
-      C64[base + e] = o;
-    }
+    double o = in ? alpha * ((double)RR[g] + acc) : 0.0;
+    if (beta != 0.0) o += beta * C64[g];
+    C64[g] = o;
   }
 }
 
@@ -854,20 +888,60 @@ void offsite_f32(const lsdm_pattern* p, const double* in, float* out, hipStream_
                      p->d_squad.as<i32>(), p->d_simg.as<i32>(), p->sys->d_patom.as<i32>(), p->n_strips);
 }
 
-void rc_correct(const lsdm_plan* pl, const double* A64, const double* B64, const float* RR, double* C64, double alpha,
+static void rc_maps(lsdm_plan* pl) {
+  std::lock_guard<std::mutex> lk(pl->rc_mutex);
+  if (pl->rc_ready) return;
+  const lsdm_pattern* C = pl->C;
+  const lsdm_system* s = C->sys;
+  int np = 1;
+  for (i32 v : s->npseudo) np = std::max(np, (int)v);
+  pl->rc_np = np;
+  pl->d_rc_b.alloc(sizeof(i32) * std::max<i64>(1, C->n_strips * 4 * np));
+  pl->d_rc_a.alloc(sizeof(i32) * std::max<i64>(1, C->n_strips * 4 * np));
+  pl->d_rc_aon.alloc(sizeof(i32) * std::max<i64>(1, (i64)s->n_pseudo * np));
+  pl->d_rc_bon.alloc(sizeof(i32) * std::max<i64>(1, (i64)s->n_pseudo * np));
+  const dim3 b(256);
+  if (C->n_strips) {
+    if (pl->transA)
+      hipLaunchKernelGGL((k_rc_map<true>), dim3(grid_for(C->n_strips * 4)), b, 0, 0, patdev(pl->A), patdev(pl->B),
+                         patdev(C), C->d_srow.as<i32>(), s->d_patom.as<i32>(), s->d_pbase.as<i32>(),
+                         s->d_npseudo.as<i32>(), np, C->n_strips, pl->d_rc_b.as<i32>(), pl->d_rc_a.as<i32>());
+    else
+      hipLaunchKernelGGL((k_rc_map<false>), dim3(grid_for(C->n_strips * 4)), b, 0, 0, patdev(pl->A), patdev(pl->B),
+                         patdev(C), C->d_srow.as<i32>(), s->d_patom.as<i32>(), s->d_pbase.as<i32>(),
+                         s->d_npseudo.as<i32>(), np, C->n_strips, pl->d_rc_b.as<i32>(), pl->d_rc_a.as<i32>());
+  }
+  if (pl->transA)
+    hipLaunchKernelGGL((k_rc_onsite<true>), dim3(grid_for((i64)s->n_pseudo * np)), b, 0, 0, patdev(pl->A),
+                       patdev(pl->B), s->d_patom.as<i32>(), s->d_pbase.as<i32>(), s->d_npseudo.as<i32>(), np,
+                       s->n_pseudo, pl->d_rc_aon.as<i32>(), pl->d_rc_bon.as<i32>());
+  else
+    hipLaunchKernelGGL((k_rc_onsite<false>), dim3(grid_for((i64)s->n_pseudo * np)), b, 0, 0, patdev(pl->A),
+                       patdev(pl->B), s->d_patom.as<i32>(), s->d_pbase.as<i32>(), s->d_npseudo.as<i32>(), np,
+                       s->n_pseudo, pl->d_rc_aon.as<i32>(), pl->d_rc_bon.as<i32>());
+  HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipDeviceSynchronize());
+  pl->rc_ready = true;
+}
+
+void rc_correct(const lsdm_plan* cpl, const double* A64, const double* B64, const float* RR, double* C64, double alpha,
                 double beta, hipStream_t st) {
+  lsdm_plan* pl = const_cast<lsdm_plan*>(cpl);
   const lsdm_pattern* C = pl->C;
   if (C->n_strips == 0) return;
+  rc_maps(pl);
   const lsdm_system* s = C->sys;
-  const dim3 g(grid_for(C->n_strips * 4)), b(256);
+  const dim3 g(grid_for(C->n_strips * 64)), b(256);
   if (pl->transA)
-    hipLaunchKernelGGL((k_rc_correct<true>), g, b, 0, st, patdev(pl->A), patdev(pl->B), patdev(C), C->d_srow.as<i32>(),
-                       A64, B64, RR, C64, s->d_patom.as<i32>(), s->d_pbase.as<i32>(), s->d_npseudo.as<i32>(),
-                       C->n_strips, alpha, beta);
+    hipLaunchKernelGGL((k_rc_apply<true>), g, b, 0, st, C->d_smask.as<uint8_t>(), C->d_srow.as<i32>(),
+                       C->d_squad.as<i32>(), C->d_simg.as<i32>(), s->d_patom.as<i32>(), pl->rc_np,
+                       pl->d_rc_b.as<i32>(), pl->d_rc_a.as<i32>(), pl->d_rc_aon.as<i32>(), pl->d_rc_bon.as<i32>(), A64,
+                       B64, RR, C64, C->n_strips, alpha, beta);
   else
-    hipLaunchKernelGGL((k_rc_correct<false>), g, b, 0, st, patdev(pl->A), patdev(pl->B), patdev(C), C->d_srow.as<i32>(),
-                       A64, B64, RR, C64, s->d_patom.as<i32>(), s->d_pbase.as<i32>(), s->d_npseudo.as<i32>(),
-                       C->n_strips, alpha, beta);
+    hipLaunchKernelGGL((k_rc_apply<false>), g, b, 0, st, C->d_smask.as<uint8_t>(), C->d_srow.as<i32>(),
+                       C->d_squad.as<i32>(), C->d_simg.as<i32>(), s->d_patom.as<i32>(), pl->rc_np,
+                       pl->d_rc_b.as<i32>(), pl->d_rc_a.as<i32>(), pl->d_rc_aon.as<i32>(), pl->d_rc_bon.as<i32>(), A64,
+                       B64, RR, C64, C->n_strips, alpha, beta);
 }
 
 void to_bf16(const float* in, unsigned short* outR, unsigned short* outC, i64 n, hipStream_t st) {

@@ -172,6 +172,14 @@ struct lsdm_plan {
   // group tiles and their steps
   lsdm::i64 n_gtiles = 0, n_gsteps = 0;
   lsdm::DevBuf d_gtiles, d_gsteps;
+  // residual mode (built on first use): for every output block, the B blocks
+  // (p', q, n) with p' in p's atom and the op(A) blocks (p, q', n) with q' in
+  // q's atom (rc_np per block, block index = value offset / 16, -1 if absent);
+  // per pseudo-atom the on-site blocks op(A)_{p,p',0} and B_{q',q,0}
+  int rc_np = 0;
+  lsdm::DevBuf d_rc_b, d_rc_a, d_rc_aon, d_rc_bon;
+  bool rc_ready = false;
+  std::mutex rc_mutex;
   // for a transposed B the plan multiplies by a materialised transpose
   lsdm::DevBuf d_bT;                // strip-layout workspace of B^T (doubles)
 };
