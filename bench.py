@@ -91,6 +91,8 @@ def cpu_baseline(cfg, flops_per_atom):
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_0911_3584_amd", "csrc", "kernels.hip")
+PRODUCT_KERNEL = {"fp64": "k_gprod<double>", "fp32": "k_gprod<float>", "bf16": "k_gprod_bf16",
+                  "fp32_rc": "k_gprod<float> (R_A R_B; FP64 corrections in k_rc_apply not counted)"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_si32768.json")
 
 
@@ -254,7 +256,8 @@ def main():
                    "fns_per_atom": "4" if args.config != 5 else "13/5", "flop_per_step": flops,
                    "triples_per_step": n_triples, "symbolic_s": round(t_sym, 2), "parallelism": "single GPU"},
         "modes": {m: {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()} for m, r in res.items()},
-        "roofline": {"kernel": f"k_prod_{args.prec} (all 8 product launches of a step)", "bound": "mfma",
+        "roofline": {"kernel": f"{PRODUCT_KERNEL[args.prec]} (all 8 product launches of a step; traffic in "
+                               f"HBM bytes per step)", "bound": "mfma",
                      "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": traffic_per_step(args.prec),
                      "per_product": per_product},

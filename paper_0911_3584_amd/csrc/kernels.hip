@@ -206,42 +206,295 @@ __global__ void __launch_bounds__(256) k_plan_gsteps(const GTile* __restrict__ t
 //
 // A workgroup of GQ = 4 wavefronts owns one group tile at a time: 16 output
 // rows (wavefront w: row quad w) x GJ column quads.  The tile's steps are
-// processed in batches of SB.  For each batch the workgroup stages in LDS the
-// step records and every operand the batch touches: per step the 16 A blocks
-// of the group's rows and the GJ B strips, each fetched from global memory
-// once for all four wavefronts (16 bytes per lane, 1 KB per instruction).
-// Software pipeline, one workgroup barrier per batch q:
-//   after the barrier: operands of q and records of q+1 are in LDS, and every
-//   wavefront is done with batch q-1;
-//   issue the global loads of records q+2 and operands q+1 (registers), run
-//   the MFMAs of batch q from LDS, then store the loaded values into the LDS
-//   slots batch q-1 used.
+// processed in batches of SB.  Every batch's step records and operands (per
+// step the 16 A blocks of the group's rows and the GJ B strips, each fetched
+// once for all four wavefronts) are copied from global memory straight into
+// LDS (global_load_lds, 16 bytes per lane, 1 KB per instruction), with no
+// register staging.  Software pipeline with lookahead DA, one workgroup
+// barrier per batch q:
+//   top of batch q (after waiting for this wavefront's copies of operands q
+//   and records q+DA, and the barrier): every wavefront is done with batch
+//   q-1, so its LDS slots may be refilled;
+//   copy records q+DA+1 (wavefront 0) and operands q+DA (addresses from
+//   records q+DA in LDS), then run the MFMAs of batch q from LDS.
+// The copies run DA batches ahead of the MFMAs while the MFMAs read other
+// LDS slots; the waits that make a slot readable are the explicit ones at the
+// top of each batch.
 // Rows without an A block are zeroed when the operand is read from LDS; a
 // column whose B strip is absent has no active slot and issues no MFMA.
 // ---------------------------------------------------------------------------
-// Steps per staged batch (LDS: 2 x SB steps of A and B operands).  Measured
-// on the 32768-atom RL16 chain: smaller batches with more resident
-// workgroups beat larger batches or a second batch of loads in flight.
+// Steps per staged batch and copy lookahead (LDS per workgroup: (DA+1) SB
+// steps of operands and (DA+2) SB records).
 #ifndef LSDM_GSB_F32
 #define LSDM_GSB_F32 4
 #endif
 #ifndef LSDM_GSB_F64
-#define LSDM_GSB_F64 4
+#define LSDM_GSB_F64 2
+#endif
+#ifndef LSDM_GDA
+#define LSDM_GDA 1
 #endif
 template <class T> struct GCfg;
 template <> struct GCfg<float> { static constexpr int SB = LSDM_GSB_F32; };
 template <> struct GCfg<double> { static constexpr int SB = LSDM_GSB_F64; };
 
 typedef int i4v __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void glb_void_t;
+
+// 16 bytes per lane from global memory to LDS at dst + 16 * lane
+__device__ __forceinline__ void copy16(const void* src, void* dst) {
+  __builtin_amdgcn_global_load_lds((glb_void_t*)src, (lds_void_t*)dst, 16, 0, 0);
+}
+// s_waitcnt immediates (gfx9 encoding): vmcnt(n) alone, lgkmcnt(0) alone
+constexpr int waitcnt_vm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x70 | 0xF00; }
+constexpr int WAIT_LGKM0 = 15 | (3 << 14) | 0x70;
+
+template <class T>
+struct GLayout {
+  static constexpr int SB = GCfg<T>::SB;
+  static constexpr int DA = LSDM_GDA;
+  static constexpr int NDS = DA + 1;          // operand slots
+  static constexpr int NRS = DA + 2;          // record slots
+  static constexpr int AV = GROWS * 16;       // A values of one step
+  static constexpr int BV = GJ * 64;          // B values of one step
+  static constexpr int SV = AV + BV;
+  static constexpr int VPL = 16 / (int)sizeof(T);
+  static constexpr int PV = 64 * VPL;         // values of one 1 KB piece
+  static constexpr int PPS = SV / PV;         // pieces per step
+  static constexpr int NPW = SB * PPS / GQ;   // pieces per wavefront and batch
+  static constexpr int RW = 32;               // dwords per record
+  static constexpr int RLANES = SB * RW / 4;  // lanes of the record copy
+  static_assert(AV % PV == 0 && BV % PV == 0 && (SB * PPS) % GQ == 0 && RLANES <= 64 && DA >= 1, "staging");
+};
+
+// LDS reads of the batch function are written out with their wait in the
+// same asm statement: the compiler, which cannot tell them apart from the
+// copies still in flight into other slots, would otherwise wait for every
+// copy before each read.  Their outputs are early-clobber: a statement issues
+// several reads, so no output may share a register with an address input.
+typedef __attribute__((address_space(3))) char lds_char;
+__device__ __forceinline__ uint32_t lds_off(const void* p) { return (uint32_t)(uintptr_t)(const lds_char*)p; }
+// A operand at a, the 8 B operands at b + 64 j values
+template <class T>
+__device__ __forceinline__ void lds_operands(uint32_t a, uint32_t b, T& av, T (&bv)[GJ]);
+template <>
+__device__ __forceinline__ void lds_operands<float>(uint32_t a, uint32_t b, float& av, float (&bv)[GJ]) {
+  static_assert(GJ == 8, "operand read layout");
+  asm volatile(
+      "ds_read_b32 %0, %9\n\t"
+      "ds_read_b32 %1, %10\n\t"
+      "ds_read_b32 %2, %10 offset:256\n\t"
+      "ds_read_b32 %3, %10 offset:512\n\t"
+      "ds_read_b32 %4, %10 offset:768\n\t"
+      "ds_read_b32 %5, %10 offset:1024\n\t"
+      "ds_read_b32 %6, %10 offset:1280\n\t"
+      "ds_read_b32 %7, %10 offset:1536\n\t"
+      "ds_read_b32 %8, %10 offset:1792\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(av), "=&v"(bv[0]), "=&v"(bv[1]), "=&v"(bv[2]), "=&v"(bv[3]), "=&v"(bv[4]), "=&v"(bv[5]),
+        "=&v"(bv[6]), "=&v"(bv[7])
+      : "v"(a), "v"(b));
+}
+template <>
+__device__ __forceinline__ void lds_operands<double>(uint32_t a, uint32_t b, double& av, double (&bv)[GJ]) {
+  static_assert(GJ == 8, "operand read layout");
+  asm volatile(
+      "ds_read_b64 %0, %9\n\t"
+      "ds_read_b64 %1, %10\n\t"
+      "ds_read_b64 %2, %10 offset:512\n\t"
+      "ds_read_b64 %3, %10 offset:1024\n\t"
+      "ds_read_b64 %4, %10 offset:1536\n\t"
+      "ds_read_b64 %5, %10 offset:2048\n\t"
+      "ds_read_b64 %6, %10 offset:2560\n\t"
+      "ds_read_b64 %7, %10 offset:3072\n\t"
+      "ds_read_b64 %8, %10 offset:3584\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(av), "=&v"(bv[0]), "=&v"(bv[1]), "=&v"(bv[2]), "=&v"(bv[3]), "=&v"(bv[4]), "=&v"(bv[5]),
+        "=&v"(bv[6]), "=&v"(bv[7])
+      : "v"(a), "v"(b));
+}
+
+// One batch of a group tile: copies for later batches, then the MFMAs of
+// this one (see k_gprod).  ring: the workgroup's LDS ring; slot arguments are
+// byte offsets into it.
+template <class T, bool TA>
+__device__ __forceinline__ void gbatch(char* ring, int rec_cur, int op_cur, int rec_addr, int op_dst, int rec_dst,
+                                       const char* rec_src, bool do_rec, bool do_ops, int nv,
+                                       const T* __restrict__ A, const T* __restrict__ B, int na_blk, int nb_str,
+                                       typename Mma16<T>::acc_t (&acc)[GJ], int lane, int wave, int a_off, int b_off,
+                                       int abit) {
+  typedef GLayout<T> L;
+  constexpr uint32_t COL = 1u | (1u << GJ) | (1u << (2 * GJ)) | (1u << (3 * GJ));
+  const uint32_t base = lds_off(ring);
+  static_assert(L::NPW == 3, "record field reads below");
+  // the operand indices of this wavefront's pieces (records of batch q+DA)
+  // and the slot masks / row bits of batch q (lane r < SB: mask of step r,
+  // lane SB + r: row bits of step r), all read in one statement
+  int fa[L::NPW];
+#pragma unroll
+  for (int i = 0; i < L::NPW; ++i) {
+    const int p = L::NPW * wave + i;
+    const int r = p / L::PPS, part = p % L::PPS;
+    const int off = part * L::PV + lane * L::VPL;
+    const int field = part * L::PV < L::AV ? (off >> 4) : GROWS + ((off - L::AV) >> 6);
+    fa[i] = base + rec_addr + 4 * (r * L::RW + field);
+  }
+  const int mfield = lane < L::SB ? lane * L::RW + GROWS + GJ + wave : (lane - L::SB) * L::RW + GROWS + GJ + GQ;
+  const uint32_t ma = base + rec_cur + 4 * (lane < 2 * L::SB ? mfield : 0);
+  int idx[L::NPW], mr;
+  asm volatile(
+      "ds_read_b32 %0, %4\n\t"
+      "ds_read_b32 %1, %5\n\t"
+      "ds_read_b32 %2, %6\n\t"
+      "ds_read_b32 %3, %7\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(idx[0]), "=&v"(idx[1]), "=&v"(idx[2]), "=&v"(mr)
+      : "v"(fa[0]), "v"(fa[1]), "v"(fa[2]), "v"(ma));
+  if (do_rec && wave == 0 && lane < L::RLANES) copy16(rec_src + 16 * lane, ring + rec_dst);
+  if (do_ops) {
+#pragma unroll
+    for (int i = 0; i < L::NPW; ++i) {
+      const int p = L::NPW * wave + i;
+      const int r = p / L::PPS, part = p % L::PPS;
+      const int off = part * L::PV + lane * L::VPL;
+      // absent operands (-1) read block 0; indices are clamped to the arrays
+      const T* src = part * L::PV < L::AV ? A + (i64)min(max(idx[i], 0), na_blk - 1) * 16 + (off & 15)
+                                          : B + (i64)min(max(idx[i], 0), nb_str - 1) * 64 + ((off - L::AV) & 63);
+      copy16(src, ring + op_dst + (r * L::SV + part * L::PV) * (int)sizeof(T));
+    }
+  }
+  if (nv <= 0) return;
+#pragma unroll 1
+  for (int r = 0; r < L::SB; ++r) {
+    uint32_t mask = (uint32_t)__builtin_amdgcn_readlane(mr, r);
+    const uint32_t rows = (uint32_t)__builtin_amdgcn_readlane(mr, L::SB + r);
+    if (r >= nv) mask = 0u;
+    if (mask == 0u) continue;
+    const uint32_t sA = base + op_cur + r * L::SV * (int)sizeof(T);
+    T av, bv[GJ];
+    lds_operands<T>(sA + a_off * (int)sizeof(T), sA + (L::AV + b_off) * (int)sizeof(T), av, bv);
+    av = ((rows >> abit) & 1u) ? av : (T)0;
+#pragma unroll
+    for (int j = 0; j < GJ; ++j)
+      if ((mask >> j) & COL) acc[j] = Mma16<T>::mma(av, bv[j], acc[j]);
+  }
+}
 
 template <class T, bool TA>
 __global__ void __launch_bounds__(256) k_gprod(const GTile* __restrict__ tiles, i64 ntiles,
                                                const GStep* __restrict__ steps, const T* __restrict__ A,
                                                const T* __restrict__ B, T* __restrict__ C,
-                                               const uint8_t* __restrict__ cmask, T alpha, T beta) {
+                                               const uint8_t* __restrict__ cmask, T alpha, T beta, int na_blk,
+                                               int nb_str) {
+  typedef typename Mma16<T>::acc_t acc_t;
+  typedef GLayout<T> L;
+  constexpr bool F64 = sizeof(T) == 8;
+  constexpr int SB = L::SB, DA = L::DA;
+  // LDS ring: NDS operand slots, then NRS record slots
+  constexpr int DSLOT = SB * L::SV * (int)sizeof(T), RSLOT = SB * L::RW * 4;
+  __shared__ __attribute__((aligned(16))) char ring[L::NDS * DSLOT + L::NRS * RSLOT];
+  auto dslot = [&](int x) { return (x % L::NDS) * DSLOT; };
+  auto rslot = [&](int x) { return L::NDS * DSLOT + (x % L::NRS) * RSLOT; };
+  // output strips of each wavefront's 4 x GJ slots and their block masks
+  __shared__ int2 cinfo[GQ][4 * GJ];
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int arow = lane & 15, ai = arow >> 2, ar = arow & 3, kk = lane >> 4;
+  const int a_off = (4 * wave + ai) * 16 + (TA ? (kk * 4 + ar) : (ar * 4 + kk));
+  const int b_off = ((lane & 15) >> 2) * 16 + kk * 4 + (lane & 3);
+  const int abit = 4 * wave + ai;
+  // contiguous tile ranges per XCD (workgroups are dealt to the 8 XCDs round
+  // robin), so concurrent tiles of one XCD share A and B through its L2
+  const i64 xcd = blockIdx.x & 7, nbx = gridDim.x >> 3, lb = blockIdx.x >> 3;
+  const i64 t_begin = ntiles * xcd / 8, t_end = ntiles * (xcd + 1) / 8;
+  const char* recs = reinterpret_cast<const char*>(steps);
+
+  for (i64 t = t_begin + lb; t < t_end; t += nbx) {
+    const GTile* tp = tiles + uniform64(t);
+    const i64 s0 = tp->step0;
+    const int ns = tp->nsteps;
+    acc_t acc[GJ];
+#pragma unroll
+    for (int q = 0; q < GJ; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[q][e] = (T)0;
+    const int nb = (ns + SB - 1) / SB;
+    auto rec_src = [&](int q) { return recs + (s0 + (i64)SB * q) * (i64)sizeof(GStep); };
+    // prologue: this wavefront's output strips and masks, records of the
+    // first DA+1 batches (every copy complete before the loop)
+    const i32 my_cs = lane < 4 * GJ ? tp->cstrip[4 * GJ * wave + lane] : -1;
+    if (wave == 0 && lane < L::RLANES)
+      for (int q = 0; q <= DA && q < nb; ++q) copy16(rec_src(q) + 16 * lane, ring + rslot(q));
+    const int mk = my_cs >= 0 ? (int)cmask[my_cs] : 0;
+    if (lane < 4 * GJ) cinfo[wave][lane] = int2{my_cs, mk};
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    // batch q runs the MFMAs of q (q >= 0) and copies operands q+DA and
+    // records q+DA+1; batches -DA .. -1 only copy
+    for (int q = -DA; q < nb; ++q) {
+      // this wavefront's copies of operands q and records q+DA are complete
+      // (copies complete in issue order; the NPW copies of operands q+DA-1,
+      // issued last in batch q-1, may remain if batch q-1 issued them)
+      asm volatile("" ::: "memory");
+      if (DA >= 2 && q > -DA && q - 1 + DA < nb)
+        __builtin_amdgcn_s_waitcnt(waitcnt_vm(L::NPW));
+      else
+        __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_s_waitcnt(WAIT_LGKM0);
+      __builtin_amdgcn_s_barrier();
+      asm volatile("" ::: "memory");
+      const int qc = q + 4 * L::NDS * L::NRS;   // non-negative for the slot arithmetic
+      gbatch<T, TA>(ring, rslot(qc), dslot(qc), rslot(qc + DA), dslot(qc + DA), rslot(qc + DA + 1),
+                    rec_src(q + DA + 1), q + DA + 1 < nb && q + DA + 1 > DA, q + DA < nb,
+                    q >= 0 ? ns - SB * q : 0, A, B, na_blk, nb_str, acc, lane, wave, a_off, b_off, abit);
+    }
+    // epilogue: lane l, register v holds D[row][col]; f32 row = 4 (l/16) + v,
+    // f64 row = 4 v + l/16; col = l % 16 (block t = col / 4, c = col % 4)
+    {
+      const int col = lane & 15, tb = col >> 2, cc = col & 3;
+#pragma unroll
+      for (int j = 0; j < GJ; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = F64 ? v : (lane >> 4);
+          const int rr = F64 ? (lane >> 4) : v;
+          const int2 ci = cinfo[wave][GJ * i + j];
+          if (ci.x < 0) continue;
+          const i64 idx = (i64)ci.x * 64 + tb * 16 + rr * 4 + cc;
+          T o = ((ci.y >> tb) & 1) ? alpha * acc[j][v] : (T)0;
+          if (beta != (T)0) o += beta * C[idx];
+          C[idx] = o;
+        }
+    }
+    // the next tile's prologue rewrites record slots and cinfo
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Register-staged variant of the group-tile product (used for FP32): the
+// same tiles and steps, operands of batch q+1 loaded into registers while
+// batch q runs and stored to LDS at its end, 2 LDS slots, one batch ahead.
+// Measured on the 32768-atom RL16 chain it beats the direct-to-LDS copies in
+// FP32 (more resident workgroups at its LDS and register use); FP64 prefers
+// the direct copies (its staging registers would cost occupancy).
+// ---------------------------------------------------------------------------
+#ifndef LSDM_GSB_RS
+#define LSDM_GSB_RS 4
+#endif
+
+template <class T, bool TA>
+__global__ void __launch_bounds__(256) k_gprod_rs(const GTile* __restrict__ tiles, i64 ntiles,
+                                               const GStep* __restrict__ steps, const T* __restrict__ A,
+                                               const T* __restrict__ B, T* __restrict__ C,
+                                               const uint8_t* __restrict__ cmask, T alpha, T beta, int na_blk,
+                                               int nb_str) {
   typedef typename Mma16<T>::acc_t acc_t;
   constexpr bool F64 = sizeof(T) == 8;
-  constexpr int SB = GCfg<T>::SB;
+  constexpr int SB = LSDM_GSB_RS;
   constexpr int AV = GROWS * 16;        // A values of one step
   constexpr int BV = GJ * 64;           // B values of one step
   constexpr int SV = AV + BV;
@@ -305,8 +558,8 @@ __global__ void __launch_bounds__(256) k_gprod(const GTile* __restrict__ tiles, 
       for (int i = 0; i < NPW; ++i) {
         const int part = i % PPS;
         const int off = part * PV + lane * VPL;
-        const T* src = part * PV < AV ? A + (i64)max(idx[i], 0) * 16 + (off & 15)
-                                      : B + (i64)max(idx[i], 0) * 64 + ((off - AV) & 63);
+        const T* src = part * PV < AV ? A + (i64)min(max(idx[i], 0), na_blk - 1) * 16 + (off & 15)
+                                      : B + (i64)min(max(idx[i], 0), nb_str - 1) * 64 + ((off - AV) & 63);
         d[i] = *reinterpret_cast<const i4v*>(src);
       }
     };
@@ -858,12 +1111,23 @@ void product(const lsdm_plan* pl, const T* A, const T* B, T* C, double alpha, do
   const GTile* Tl = pl->d_gtiles.as<GTile>();
   const GStep* S = pl->d_gsteps.as<GStep>();
   const dim3 b(256);
-  if (pl->transA)
-    hipLaunchKernelGGL((k_gprod<T, true>), dim3(gproduct_grid(k_gprod<T, true>, pl->n_gtiles)), b, 0, st, Tl,
-                       pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta);
-  else
-    hipLaunchKernelGGL((k_gprod<T, false>), dim3(gproduct_grid(k_gprod<T, false>, pl->n_gtiles)), b, 0, st, Tl,
-                       pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta);
+  // operand array bounds for the index clamp (a plan with steps has both)
+  const int na = (int)std::max<i64>(1, pl->A->n_strips * 4), nbs = (int)std::max<i64>(1, pl->B->n_strips);
+  if constexpr (sizeof(T) == 4) {
+    if (pl->transA)
+      hipLaunchKernelGGL((k_gprod_rs<T, true>), dim3(gproduct_grid(k_gprod_rs<T, true>, pl->n_gtiles)), b, 0, st, Tl,
+                         pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta, na, nbs);
+    else
+      hipLaunchKernelGGL((k_gprod_rs<T, false>), dim3(gproduct_grid(k_gprod_rs<T, false>, pl->n_gtiles)), b, 0, st,
+                         Tl, pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta, na, nbs);
+  } else {
+    if (pl->transA)
+      hipLaunchKernelGGL((k_gprod<T, true>), dim3(gproduct_grid(k_gprod<T, true>, pl->n_gtiles)), b, 0, st, Tl,
+                         pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta, na, nbs);
+    else
+      hipLaunchKernelGGL((k_gprod<T, false>), dim3(gproduct_grid(k_gprod<T, false>, pl->n_gtiles)), b, 0, st, Tl,
+                         pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta, na, nbs);
+  }
 }
 template void product<double>(const lsdm_plan*, const double*, const double*, double*, double, double, hipStream_t);
 template void product<float>(const lsdm_plan*, const float*, const float*, float*, double, double, hipStream_t);

@@ -134,7 +134,10 @@ constexpr int GQ = 4;
 constexpr int GJ = 8;
 constexpr int GROWS = 4 * GQ;
 // groups per super-group of the tile traversal order
-constexpr int GSUPER = 4;
+#ifndef LSDM_GSUPER
+#define LSDM_GSUPER 4
+#endif
+constexpr int GSUPER = LSDM_GSUPER;
 
 struct GTile {
   i32 group;            // rows 4*GQ*group .. +4*GQ-1
