@@ -91,8 +91,8 @@ def cpu_baseline(cfg, flops_per_atom):
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_0911_3584_amd", "csrc", "kernels.hip")
-PRODUCT_KERNEL = {"fp64": "k_gprod<double>", "fp32": "k_gprod<float>", "bf16": "k_gprod_bf16",
-                  "fp32_rc": "k_gprod<float> (R_A R_B; FP64 corrections in k_rc_apply not counted)"}
+PRODUCT_KERNEL = {"fp64": "k_gprod<double>", "fp32": "k_gprod_rs<float>", "bf16": "k_gprod_bf16",
+                  "fp32_rc": "k_gprod_rs<float> (R_A R_B; FP64 corrections in k_rc_apply not counted)"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_si32768.json")
 
 
