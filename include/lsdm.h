@@ -167,6 +167,45 @@ int lsdm_lnv_energy(lsdm_lnv* lnv, int prec, const double* dL, const double* dS,
  * precision mode as the forward products.  dGradL: device. */
 int lsdm_lnv_energy_grad(lsdm_lnv* lnv, int prec, const double* dL, const double* dS, const double* dH,
                          double* dE, double* dGradL, void* stream);
+/* Exact line search (section 2: the ground state is the minimum of E over L;
+ * eq. 3 makes E a cubic polynomial of L).  coeffs[0..3] (host) receive c0..c3
+ * of E(L + tD) = c0 + c1 t + c2 t^2 + c3 t^3, obtained from the energies at
+ * t = -h, 0, h, 2h (exact for a cubic up to rounding; choose h near the
+ * expected step).  dL, dD: device, L's pattern.  Synchronises the stream.
+ * Errors: LSDM_EINVAL (null pointer, h not finite or <= 0), LSDM_EDEVICE. */
+int lsdm_lnv_line(lsdm_lnv* lnv, int prec, const double* dL, const double* dD, const double* dS, const double* dH,
+                  double h, double* coeffs, void* stream);
+/* Minimise E over L (in place, device, L's pattern) by Polak-Ribiere
+ * conjugate gradients (beta clipped at 0, restart when the direction is not a
+ * descent direction) with the exact line search above: each step goes to the
+ * local minimum of the cubic along the direction (h = h0 for the first line,
+ * then the previous step; if the cubic has no local minimum the step is h).
+ * Inside the loop c0 and c1 = <dE/dL, D> are known, so each line costs two
+ * chain evaluations (t = -h, h) on top of one energy-and-gradient pass.
+ * Stops after max_iter steps or when |dE/dL| <= gtol (Frobenius norm over L's
+ * stored values).  Host outputs: E_hist[0..iters] and gnorm_hist[0..iters]
+ * (sized max_iter + 1), iters.  Scalars are read back every step.
+ * Errors: LSDM_EINVAL, LSDM_ENOMEM, LSDM_EDEVICE. */
+int lsdm_lnv_minimise(lsdm_lnv* lnv, int prec, double* dL, const double* dS, const double* dH, int max_iter,
+                      double gtol, double h0, double* E_hist, double* gnorm_hist, int* iters, void* stream);
+/* Chemical potential (section 2, constraint 2 on the electron number): with
+ * H' = H - mu S the chain's energy is 2 Tr[K(H - mu S)] = E - mu N_e, so the
+ * calls above evaluate and minimise the grand potential at fixed mu.
+ * dOut = beta dH + alpha dS on H's pattern (device, H's value layout; S's
+ * blocks are added at their place in H).  dH may be NULL when beta = 0 and may
+ * equal dOut.  Asynchronous on the stream; the first call on a handle builds a
+ * block map (synchronous).  Errors: LSDM_EINVAL, LSDM_EPATTERN (rS > rH: S's
+ * pattern is not inside H's), LSDM_EDEVICE. */
+int lsdm_lnv_shift(lsdm_lnv* lnv, double alpha, const double* dS, double beta, const double* dH, double* dOut,
+                   void* stream);
+/* Electron number N_e = 2 Tr(KS) with K of eq. 3 on H's range (section 2,
+ * constraint 2), written to dN (device, one double), and optionally
+ * dGradN = dN_e/dL on L's pattern (device, NULL to skip), in precision mode
+ * prec.  Uses a workspace of H's size held by the handle; calls on one handle
+ * must not overlap.  Errors: LSDM_EINVAL, LSDM_EPATTERN (rS > rH), LSDM_ENOMEM,
+ * LSDM_EDEVICE. */
+int lsdm_lnv_electrons(lsdm_lnv* lnv, int prec, const double* dL, const double* dS, double* dN, double* dGradN,
+                       void* stream);
 /* Kernel timing of the chain's products: with enable = 1 every product launch
  * of lsdm_lnv_energy(_grad) is bracketed by HIP events recorded on the call's
  * stream (no extra synchronisation); enable = 0 stops and discards. */

@@ -15,10 +15,14 @@ What it computes (Bowler & Miyazaki, section 2 "Methodology"):
   range pattern (matrix multiplication, item 1 of the list of operations);
 * the LNV (McWeeny) density matrix of eq. 3, K = 3 LSL - 2 LSLSL, on H's range;
 * the energy E = 2 Tr(KH) with the spin factor of the electron count
-  N_e = 2 Tr(KS) (constraint 2 of the ground-state search);
+  N_e = 2 Tr(KS) (constraint 2 of the ground-state search), N_e itself, and the
+  shifted Hamiltonian H - mu S of a chemical potential;
 * dE/dL on L's range, by the analytic formula
   6 (HLS + SLH) - 4 (HLSLS + SLHLS + SLSLH) evaluated through an evaluation
-  order different from the forward chain.
+  order different from the forward chain;
+* the minimisation of E over L (the ground-state search of section 2): the
+  coefficients of the cubic E(L + tD), expanded term by term from eq. 3, and a
+  conjugate-gradient loop whose steps go to the cubic's local minimum.
 
 Readings where the paper is silent are listed in the design notes; the ones that
 shape this code: intermediate ranges follow the "needed range" rule
@@ -372,3 +376,92 @@ def multiply_adjoint(A: Matrix, transA: bool, B: Matrix, transB: bool, Cbar: Mat
     Abar = multiply(opB, CbT, pA) if transA else (multiply(Cbar, B, pA) if transB else multiply_nt(Cbar, B, pA))
     Bbar = multiply(CbT, opA, pB) if transB else multiply(opAT, Cbar, pB)
     return Abar, Bbar
+
+
+# ---------------------------------------------------------------------------
+# minimisation of E over L (section 2, the ground-state search)
+# ---------------------------------------------------------------------------
+def shift(H: Matrix, S: Matrix, mu: float) -> Matrix:
+    """H - mu S on H's range: with it the energy 2 Tr[K(H - mu S)] = E - mu N_e
+    is the grand potential at chemical potential mu (constraint 2 of section 2
+    imposed through mu)."""
+    return Matrix(H.pattern, H.val - mu * project(S, H.pattern).val)
+
+
+def electron_number(L: Matrix, S: Matrix, rS, rH, rL) -> float:
+    """N_e = 2 Tr(KS) (constraint 2 of section 2) with K of eq. 3 on H's range;
+    Tr(KS) = sum over stored blocks of K_ij . S_ij for symmetric S."""
+    pH = pattern(L.pattern.system, rH)
+    K = lnv_energy(L, S, zeros(pH), rS, rH, rL)["K"]
+    return 2.0 * dot(K.val, project(S, pH).val)
+
+
+def lnv_line_coeffs(L: Matrix, D: Matrix, S: Matrix, H: Matrix, rS, rH, rL) -> np.ndarray:
+    """c0..c3 of E(L + tD) = c0 + c1 t + c2 t^2 + c3 t^3, expanded from eq. 3
+    with L_t = L + tD (literal products, valid for any L and D on L's range):
+      L_t S L_t       = LSL + t (LSD + DSL) + t^2 DSD
+      L_t S L_t S L_t = LSLSL + t (LSLSD + LSDSL + DSLSL)
+                        + t^2 (LSDSD + DSLSD + DSDSL) + t^3 DSDSD
+    and E(t) = 2 <3 L_t S L_t - 2 L_t S L_t S L_t, H> on H's range."""
+    sysm = L.pattern.system
+    R = chain_ranges(rS, rH, rL)
+    pX, pM, pH = pattern(sysm, R["X"]), pattern(sysm, R["M"]), pattern(sysm, rH)
+    LS, DS = multiply(L, S, pX), multiply(D, S, pX)
+    SL, SD = multiply(S, L, pX), multiply(S, D, pX)
+    LSL, LSD, DSL, DSD = (multiply(LS, L, pM), multiply(LS, D, pM), multiply(DS, L, pM), multiply(DS, D, pM))
+
+    def h(m):            # <m, H> on H's range, m on M's or H's range
+        return dot(project(m, pH).val, project(H, pH).val)
+
+    def five(a, b):      # <a b, H>, a on M's range, b on X's range
+        return dot(multiply(a, b, pH).val, project(H, pH).val)
+
+    c0 = 2.0 * (3.0 * h(LSL) - 2.0 * five(LSL, SL))
+    c1 = 2.0 * (3.0 * (h(LSD) + h(DSL)) - 2.0 * (five(LSL, SD) + five(LSD, SL) + five(DSL, SL)))
+    c2 = 2.0 * (3.0 * h(DSD) - 2.0 * (five(LSD, SD) + five(DSL, SD) + five(DSD, SL)))
+    c3 = 2.0 * (-2.0 * five(DSD, SD))
+    return np.array([c0, c1, c2, c3])
+
+
+def cubic_step(c, h: float) -> float:
+    """Step t > 0 to the local minimum of c1 t + c2 t^2 + c3 t^3 along a descent
+    direction: the root of c1 + 2 c2 t + 3 c3 t^2 = 0 where the second
+    derivative 2 c2 + 6 c3 t is positive; t = h when there is none."""
+    c1, c2, c3 = float(c[1]), float(c[2]), float(c[3])
+    disc = c2 * c2 - 3.0 * c1 * c3
+    t = -1.0
+    if disc >= 0.0 and c2 + np.sqrt(disc) > 0.0:
+        t = -c1 / (c2 + np.sqrt(disc))
+    if not (t > 0.0) or not np.isfinite(t):
+        t = h
+    return t
+
+
+def lnv_minimise(L: Matrix, S: Matrix, H: Matrix, rS, rH, rL, max_iter: int, gtol: float = 0.0, h0: float = 1.0):
+    """Polak-Ribiere conjugate gradients on E(L) (beta clipped at 0, restart on
+    a non-descent direction), each step exact along its line (the cubic's
+    local minimum, first trial scale h0, then the previous step).
+    Returns (L_final, energies, gradient norms), the first entries at the start.
+    For symmetric L, S, H the gradient stays symmetric."""
+    L = Matrix(L.pattern, L.val.copy())
+    G = lnv_gradient(L, S, H, rS, rH, rL)
+    Es = [lnv_energy(L, S, H, rS, rH, rL)["E"]]
+    gs = [np.sqrt(dot(G.val, G.val))]
+    D = -G.val
+    h = h0
+    for _ in range(max_iter):
+        if gs[-1] <= gtol:
+            break
+        c = lnv_line_coeffs(L, Matrix(L.pattern, D), S, H, rS, rH, rL)
+        t = cubic_step(c, h)
+        L = Matrix(L.pattern, L.val + t * D)
+        Gn = lnv_gradient(L, S, H, rS, rH, rL)
+        Es.append(lnv_energy(L, S, H, rS, rH, rL)["E"])
+        beta = max(0.0, (dot(Gn.val, Gn.val) - dot(Gn.val, G.val)) / dot(G.val, G.val))
+        D = -Gn.val + beta * D
+        if dot(D, Gn.val) >= 0.0:
+            D = -Gn.val
+        G = Gn
+        gs.append(np.sqrt(dot(G.val, G.val)))
+        h = t
+    return L, np.array(Es), np.array(gs)

@@ -201,6 +201,47 @@ class LNV:
                                          _dev(E, 1, "E"), _dev(G, p["L"].n_values, "G"), _stream(stream)))
         return E, G
 
+    def line(self, L, D, S, H, h=1.0, prec="fp64", stream=None):
+        """Coefficients c0..c3 of E(L + tD) (numpy array, exact cubic)."""
+        p = self.patterns
+        c = np.zeros(4)
+        check(lib().lsdm_lnv_line(self._h, _prec(prec), _dev(L, p["L"].n_values, "L"), _dev(D, p["L"].n_values, "D"),
+                                  _dev(S, p["S"].n_values, "S"), _dev(H, p["H"].n_values, "H"), float(h), _ptr(c),
+                                  _stream(stream)))
+        return c
+
+    def minimise(self, L, S, H, max_iter=20, gtol=1e-8, h0=1.0, prec="fp64", stream=None):
+        """Conjugate-gradient minimisation of E over L in place; returns
+        (energies, gradient norms) per step, the first entry for the start."""
+        p = self.patterns
+        Eh = np.zeros(max_iter + 1); gh = np.zeros(max_iter + 1); it = ctypes.c_int(0)
+        check(lib().lsdm_lnv_minimise(self._h, _prec(prec), _dev(L, p["L"].n_values, "L"),
+                                      _dev(S, p["S"].n_values, "S"), _dev(H, p["H"].n_values, "H"), int(max_iter),
+                                      float(gtol), float(h0), _ptr(Eh), _ptr(gh), ctypes.byref(it), _stream(stream)))
+        return Eh[:it.value + 1], gh[:it.value + 1]
+
+    def shift(self, S, H=None, mu=0.0, out=None, stream=None):
+        """H - mu S on H's pattern (a new tensor unless `out` is given; H=None
+        gives -mu S).  The chain's energy with it is 2 Tr[K(H - mu S)]."""
+        import torch
+        p = self.patterns
+        out = torch.empty(p["H"].n_values, dtype=torch.float64, device=S.device) if out is None else out
+        check(lib().lsdm_lnv_shift(self._h, -float(mu), _dev(S, p["S"].n_values, "S"), 1.0 if H is not None else 0.0,
+                                   _dev(H, p["H"].n_values, "H") if H is not None else None,
+                                   _dev(out, p["H"].n_values, "out"), _stream(stream)))
+        return out
+
+    def electrons(self, L, S, prec="fp64", grad=False, stream=None):
+        """N_e = 2 Tr(KS) (tensor of one double), and dN_e/dL when grad=True."""
+        import torch
+        p = self.patterns
+        N = torch.empty(1, dtype=torch.float64, device=L.device)
+        G = torch.empty(p["L"].n_values, dtype=torch.float64, device=L.device) if grad else None
+        check(lib().lsdm_lnv_electrons(self._h, _prec(prec), _dev(L, p["L"].n_values, "L"),
+                                       _dev(S, p["S"].n_values, "S"), _dev(N, 1, "N"),
+                                       _dev(G, p["L"].n_values, "G") if grad else None, _stream(stream)))
+        return (N, G) if grad else N
+
     PRODUCTS = ("F1", "F2", "F3", "B1", "B2", "B3", "B4", "B5")
 
     def profile(self, enable=True):

@@ -33,6 +33,10 @@ SIGNATURES = {
     "lsdm_lnv_info": (_I, [_P, _I, _I64P, ctypes.POINTER(_D)]),
     "lsdm_lnv_energy": (_I, [_P, _I, _P, _P, _P, _P, _P, _P]),
     "lsdm_lnv_energy_grad": (_I, [_P, _I, _P, _P, _P, _P, _P, _P]),
+    "lsdm_lnv_line": (_I, [_P, _I, _P, _P, _P, _P, _D, _P, _P]),
+    "lsdm_lnv_minimise": (_I, [_P, _I, _P, _P, _P, _I, _D, _D, _P, _P, _P, _P]),
+    "lsdm_lnv_shift": (_I, [_P, _D, _P, _D, _P, _P, _P]),
+    "lsdm_lnv_electrons": (_I, [_P, _I, _P, _P, _P, _P, _P]),
     "lsdm_lnv_profile": (_I, [_P, _I]),
     "lsdm_lnv_profile_read": (_I, [_P, _P, _P, _P]),
     "lsdm_lnv_destroy": (None, [_P]),

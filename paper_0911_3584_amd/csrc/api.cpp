@@ -13,6 +13,7 @@
 //             B5  Lbar += P_L(Xbar S)
 // Taking LSLSL as X M = (LS)(LSL) keeps the chain equal to eq. 3 for any L, so
 // the adjoint yields dE/dL of eq. 3 itself: 6 (HLS + SLH) - 4 (HLSLS + SLHLS + SLSLH).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -684,6 +685,241 @@ int lsdm_lnv_info(const lsdm_lnv* L, int grad, int64_t* n_triples, double* flops
       for (auto p : b) { nt += p->n_triples; fl += p->flops; }
     if (n_triples) *n_triples = nt;
     if (flops) *flops = fl;
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Minimisation of the LNV energy over L (the search the paper runs, section 2:
+// the ground state is found by minimising E with respect to L).  Line search:
+// E(L + tD) is a cubic polynomial of t (eq. 3 is cubic in L), so one line
+// search is exact: its four coefficients come from four energies at
+// t = -h, 0, h, 2h, and the step is the cubic's local minimum.  Directions:
+// Polak-Ribiere conjugate gradients with restarts.
+// ---------------------------------------------------------------------------
+static void energy_any(lsdm_lnv* L, int prec, const double* dL, const double* dS, const double* dH, double* dE,
+                       hipStream_t st) {
+  if (prec == LSDM_FP64) lnv_forward<double>(L, dL, dS, dH, nullptr, dE, st);
+  else if (prec == LSDM_FP32) lnv_forward<float>(L, dL, dS, dH, nullptr, dE, st);
+  else if (prec == LSDM_BF16) lnv_forward_bf16(L, dL, dS, dH, nullptr, dE, st);
+  else if (prec == LSDM_FP32_RC) lnv_forward_rc(L, dL, dS, dH, nullptr, dE, st);
+  else LSDM_THROW(LSDM_EINVAL, "unknown precision mode");
+}
+static void energy_grad_any(lsdm_lnv* L, int prec, const double* dL, const double* dS, const double* dH, double* dE,
+                            double* dG, hipStream_t st) {
+  energy_any(L, prec, dL, dS, dH, dE, st);
+  if (prec == LSDM_FP64) lnv_backward<double>(L, dG, st);
+  else if (prec == LSDM_FP32) lnv_backward<float>(L, dG, st);
+  else if (prec == LSDM_BF16) lnv_backward_bf16(L, dG, st);
+  else lnv_backward_rc(L, dG, st);
+}
+static double read_scalar(const double* d, hipStream_t st) {
+  double h = 0;
+  HIP_CHECK(hipMemcpyAsync(&h, d, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  return h;
+}
+
+// coefficients c[0..3] of E(L + tD) from energies at t = -h, 0, h, 2h; Lt is
+// an L-sized workspace, dE one device double
+static void line_coeffs(lsdm_lnv* L, int prec, const double* dL, const double* dD, const double* dS, const double* dH,
+                        double h, double* c, double* Lt, double* dE, hipStream_t st) {
+  const i64 n = L->pL->nval;
+  double e[4];
+  const double ts[4] = {-1.0, 0.0, 1.0, 2.0};
+  for (int k = 0; k < 4; ++k) {
+    lincomb(Lt, dL, dD, 1.0, ts[k] * h, n, st);
+    energy_any(L, prec, Lt, dS, dH, dE, st);
+    check_launch();
+    e[k] = read_scalar(dE, st);
+  }
+  // E(s h) = a0 + a1 s + a2 s^2 + a3 s^3 through s = -1, 0, 1, 2
+  const double a0 = e[1];
+  const double a2 = 0.5 * (e[2] + e[0]) - a0;
+  const double odd = 0.5 * (e[2] - e[0]);                       // a1 + a3
+  const double a3 = (0.5 * (e[3] - a0 - 4.0 * a2) - odd) / 3.0;  // (a1 + 4 a3 - (a1 + a3)) / 3
+  const double a1 = odd - a3;
+  c[0] = a0;
+  c[1] = a1 / h;
+  c[2] = a2 / (h * h);
+  c[3] = a3 / (h * h * h);
+}
+
+// the same coefficients when c0 = E(L) and c1 = <dE/dL, D> are already known
+// (inside the minimiser): energies at t = -h and h give the even and odd parts,
+// so two chain evaluations instead of four and an exact slope
+static void line_coeffs_known(lsdm_lnv* L, int prec, const double* dL, const double* dD, const double* dS,
+                              const double* dH, double h, double c0, double c1, double* c, double* Lt, double* dE,
+                              hipStream_t st) {
+  const i64 n = L->pL->nval;
+  double e[2];
+  for (int k = 0; k < 2; ++k) {
+    lincomb(Lt, dL, dD, 1.0, (k ? 1.0 : -1.0) * h, n, st);
+    energy_any(L, prec, Lt, dS, dH, dE, st);
+    check_launch();
+    e[k] = read_scalar(dE, st);
+  }
+  c[0] = c0;
+  c[1] = c1;
+  c[2] = (0.5 * (e[1] + e[0]) - c0) / (h * h);          // c2 h^2
+  c[3] = (0.5 * (e[1] - e[0]) - c1 * h) / (h * h * h);  // c1 h + c3 h^3
+}
+
+// step to the local minimum of c1 t + c2 t^2 + c3 t^3 along a descent
+// direction (c1 < 0); fallback when the cubic has none: t = h
+static double cubic_step(const double* c, double h) {
+  const double c1 = c[1], c2 = c[2], c3 = c[3];
+  const double disc = c2 * c2 - 3.0 * c1 * c3;
+  double t = -1.0;
+  if (disc >= 0.0) {
+    const double den = c2 + std::sqrt(disc);   // the root where 2 c2 + 6 c3 t > 0
+    if (den > 0.0) t = -c1 / den;
+  }
+  if (!(t > 0.0) || !std::isfinite(t)) t = h;
+  return t;
+}
+
+int lsdm_lnv_line(lsdm_lnv* L, int prec, const double* dL, const double* dD, const double* dS, const double* dH,
+                  double h, double* coeffs, void* stream) {
+  return guarded([&] {
+    require_device();
+    if (!L || !dL || !dD || !dS || !dH || !coeffs) LSDM_THROW(LSDM_EINVAL, "null argument");
+    if (!(h > 0.0) || !std::isfinite(h)) LSDM_THROW(LSDM_EINVAL, "h must be finite and > 0");
+    hipStream_t st = (hipStream_t)stream;
+    DevBuf Lt, dE;
+    Lt.alloc(sizeof(double) * std::max<i64>(1, L->pL->nval));
+    dE.alloc(sizeof(double));
+    line_coeffs(L, prec, dL, dD, dS, dH, h, coeffs, Lt.as<double>(), dE.as<double>(), st);
+  });
+}
+
+int lsdm_lnv_minimise(lsdm_lnv* L, int prec, double* dL, const double* dS, const double* dH, int max_iter,
+                      double gtol, double h0, double* E_hist, double* gnorm_hist, int* iters, void* stream) {
+  return guarded([&] {
+    require_device();
+    if (!L || !dL || !dS || !dH || !E_hist || !gnorm_hist || !iters) LSDM_THROW(LSDM_EINVAL, "null argument");
+    if (max_iter < 0 || !(gtol >= 0.0) || !(h0 > 0.0) || !std::isfinite(h0))
+      LSDM_THROW(LSDM_EINVAL, "max_iter >= 0, gtol >= 0 and a finite h0 > 0 are required");
+    hipStream_t st = (hipStream_t)stream;
+    const i64 n = L->pL->nval;
+    const size_t nb = sizeof(double) * std::max<i64>(1, n);
+    DevBuf G, Gn, D, Lt, sc, part;
+    G.alloc(nb); Gn.alloc(nb); D.alloc(nb); Lt.alloc(nb);
+    sc.alloc(sizeof(double) * 4);
+    part.alloc(sizeof(double) * 2 * DOT_BLOCKS);
+    double* dE = sc.as<double>();
+    double* dd = sc.as<double>() + 1;
+    auto dotp = [&](const double* a, const double* b) {
+      dot(a, b, n, 1.0, part.as<double>(), dd, st);
+      return read_scalar(dd, st);
+    };
+    energy_grad_any(L, prec, dL, dS, dH, dE, G.as<double>(), st);
+    check_launch();
+    E_hist[0] = read_scalar(dE, st);
+    double g2 = dotp(G.as<double>(), G.as<double>());
+    gnorm_hist[0] = std::sqrt(g2);
+    lincomb(D.as<double>(), G.as<double>(), G.as<double>(), -1.0, 0.0, n, st);   // D = -G
+    double h = h0;
+    double slope = -g2;                                                          // <G, D>
+    int it = 0;
+    while (it < max_iter && std::sqrt(g2) > gtol) {
+      double c[4];
+      line_coeffs_known(L, prec, dL, D.as<double>(), dS, dH, h, E_hist[it], slope, c, Lt.as<double>(), dE, st);
+      const double t = cubic_step(c, h);
+      lincomb(dL, dL, D.as<double>(), 1.0, t, n, st);                            // L += t D
+      energy_grad_any(L, prec, dL, dS, dH, dE, Gn.as<double>(), st);
+      check_launch();
+      ++it;
+      E_hist[it] = read_scalar(dE, st);
+      const double gn2 = dotp(Gn.as<double>(), Gn.as<double>());
+      const double gng = dotp(Gn.as<double>(), G.as<double>());
+      const double beta = std::max(0.0, (gn2 - gng) / g2);                       // Polak-Ribiere+
+      lincomb(D.as<double>(), Gn.as<double>(), D.as<double>(), -1.0, beta, n, st);  // D = -Gn + beta D
+      slope = dotp(D.as<double>(), Gn.as<double>());
+      if (slope >= 0.0) {                                                        // not a descent direction
+        lincomb(D.as<double>(), Gn.as<double>(), Gn.as<double>(), -1.0, 0.0, n, st);
+        slope = -gn2;
+      }
+      std::swap(G.p, Gn.p);
+      g2 = gn2;
+      gnorm_hist[it] = std::sqrt(g2);
+      h = t;
+    }
+    *iters = it;
+    HIP_CHECK(hipStreamSynchronize(st));
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Electron number (section 2, constraint 2: N_e = 2 Tr(KS)).  A chemical
+// potential enters as H - mu S, so that 2 Tr[K(H - mu S)] = E - mu N_e and the
+// same chain minimises the grand potential; N_e itself is the chain's energy
+// with H replaced by S (S's range lies inside H's, and K lives on H's range).
+// ---------------------------------------------------------------------------
+static void s2h_map(lsdm_lnv* L) {
+  std::lock_guard<std::mutex> g(L->s2h_mutex);
+  if (L->s2h_ready) return;
+  const lsdm_pattern *S = L->pS, *H = L->pH;
+  const i64 nb = (i64)S->col.size();
+  std::vector<i64> so(nb), ho(nb);
+  std::vector<i32> sz(nb);
+  for (i32 i = 0; i < L->sys->n_atoms; ++i) {
+    for (i64 b = S->row_ptr[i]; b < S->row_ptr[i + 1]; ++b) {
+      const i64 key = ((i64)S->col[b] << 24) | (i64)S->img[b];
+      i64 lo = H->row_ptr[i], hi = H->row_ptr[i + 1];
+      while (lo < hi) {                       // H's rows are sorted by (column, image)
+        const i64 mid = (lo + hi) >> 1;
+        if ((((i64)H->col[mid] << 24) | (i64)H->img[mid]) < key) lo = mid + 1; else hi = mid;
+      }
+      if (lo >= H->row_ptr[i + 1] || (((i64)H->col[lo] << 24) | (i64)H->img[lo]) != key)
+        LSDM_THROW(LSDM_EPATTERN, "S's pattern is not contained in H's (rS > rH)");
+      so[b] = S->val_off[b];
+      ho[b] = H->val_off[lo];
+      sz[b] = L->sys->nfn[i] * L->sys->nfn[S->col[b]];
+    }
+  }
+  L->d_s2h_s.upload(so.data(), sizeof(i64) * nb);
+  L->d_s2h_h.upload(ho.data(), sizeof(i64) * nb);
+  L->d_s2h_n.upload(sz.data(), sizeof(i32) * nb);
+  L->n_sblk = nb;
+  L->s2h_ready = true;
+}
+
+// out = beta H + alpha S on H's pattern (dH may be null when beta = 0)
+static void shift_into(lsdm_lnv* L, double alpha, const double* dS, double beta, const double* dH, double* dOut,
+                       hipStream_t st) {
+  s2h_map(L);
+  const i64 n = L->pH->nval;
+  if (dH) lincomb(dOut, dH, dH, beta, 0.0, n, st);
+  else fill<double>(dOut, n, 0.0, st);
+  add_blocks(dOut, dS, L->d_s2h_s.as<i64>(), L->d_s2h_h.as<i64>(), L->d_s2h_n.as<i32>(), L->n_sblk, alpha, st);
+  check_launch();
+}
+
+int lsdm_lnv_shift(lsdm_lnv* L, double alpha, const double* dS, double beta, const double* dH, double* dOut,
+                   void* stream) {
+  return guarded([&] {
+    require_device();
+    if (!L || !dS || !dOut || (!dH && beta != 0.0)) LSDM_THROW(LSDM_EINVAL, "null argument");
+    if (!std::isfinite(alpha) || !std::isfinite(beta)) LSDM_THROW(LSDM_EINVAL, "alpha and beta must be finite");
+    shift_into(L, alpha, dS, beta, dH, dOut, (hipStream_t)stream);
+  });
+}
+
+int lsdm_lnv_electrons(lsdm_lnv* L, int prec, const double* dL, const double* dS, double* dN, double* dGradN,
+                       void* stream) {
+  return guarded([&] {
+    require_device();
+    if (!L || !dL || !dS || !dN) LSDM_THROW(LSDM_EINVAL, "null argument");
+    if (prec < LSDM_FP64 || prec > LSDM_FP32_RC) LSDM_THROW(LSDM_EINVAL, "unknown precision mode");
+    hipStream_t st = (hipStream_t)stream;
+    {
+      std::lock_guard<std::mutex> g(L->s2h_mutex);
+      if (!L->wSh.p) L->wSh.alloc(sizeof(double) * std::max<i64>(1, L->pH->nval));
+    }
+    shift_into(L, 1.0, dS, 0.0, nullptr, L->wSh.as<double>(), st);
+    if (dGradN) energy_grad_any(L, prec, dL, dS, L->wSh.as<double>(), dN, dGradN, st);
+    else energy_any(L, prec, dL, dS, L->wSh.as<double>(), dN, st);
+    check_launch();
   });
 }
 

@@ -36,5 +36,10 @@ template <class T> void kassembly(const lsdm_lnv* L, const T* M, const T* P, dou
 template <class T> void scatter_h(const lsdm_lnv* L, const T* H, T* Mb, double scale, hipStream_t st);
 // out[0] = scale * sum a[i] b[i]; partial holds 2 * DOT_BLOCKS doubles
 void dot(const double* a, const double* b, i64 n, double scale, double* partial, double* out, hipStream_t st);
+// out = a x + b y, n doubles
+void lincomb(double* out, const double* x, const double* y, double a, double b, i64 n, hipStream_t st);
+// out[hoff[b] + e] += a * x[xoff[b] + e] for e < size[b], b < nb (distinct target blocks)
+void add_blocks(double* out, const double* x, const i64* xoff, const i64* hoff, const i32* size, i64 nb, double a,
+                hipStream_t st);
 
 }  // namespace lsdm

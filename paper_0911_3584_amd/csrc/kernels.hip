@@ -1247,6 +1247,34 @@ void scatter_h(const lsdm_lnv* L, const T* H, T* Mb, double scale, hipStream_t s
 template void scatter_h<double>(const lsdm_lnv*, const double*, double*, double, hipStream_t);
 template void scatter_h<float>(const lsdm_lnv*, const float*, float*, double, hipStream_t);
 
+// out = a x + b y (element-wise; out may be x or y)
+__global__ void k_lincomb(double* out, const double* x, const double* y, double a, double b, i64 n) {
+  for (i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x; g < n; g += (i64)gridDim.x * blockDim.x)
+    out[g] = a * x[g] + b * y[g];
+}
+void lincomb(double* out, const double* x, const double* y, double a, double b, i64 n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_lincomb, dim3(grid_for(n)), dim3(256), 0, st, out, x, y, a, b, n);
+}
+
+// one wavefront per source block; the target blocks are distinct, so no two
+// lanes write the same value
+__global__ void k_add_blocks(double* out, const double* __restrict__ x, const i64* __restrict__ xoff,
+                             const i64* __restrict__ hoff, const i32* __restrict__ size, i64 nb, double a) {
+  const int lane = threadIdx.x & 63;
+  const i64 nw = (i64)gridDim.x * (blockDim.x >> 6);
+  for (i64 b = (blockIdx.x * (i64)blockDim.x + threadIdx.x) >> 6; b < nb; b += nw) {
+    const i64 xo = xoff[b], ho = hoff[b];
+    for (int e = lane; e < size[b]; e += 64) out[ho + e] += a * x[xo + e];
+  }
+}
+void add_blocks(double* out, const double* x, const i64* xoff, const i64* hoff, const i32* size, i64 nb, double a,
+                hipStream_t st) {
+  if (nb <= 0) return;
+  const i64 grid = std::min<i64>((nb + 3) / 4, 4096);
+  hipLaunchKernelGGL(k_add_blocks, dim3((unsigned)grid), dim3(256), 0, st, out, x, xoff, hoff, size, nb, a);
+}
+
 void dot(const double* a, const double* b, i64 n, double scale, double* partial, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_dot_partial<double>, dim3(DOT_BLOCKS), dim3(256), 0, st, a, b, n, partial);
   hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, st, partial, DOT_BLOCKS, scale, out);

@@ -207,6 +207,13 @@ struct lsdm_lnv {
   // fp32 product of the off-site parts
   lsdm::DevBuf r32[7], rr32;
   bool rc_ready = false;
+  // S's blocks inside H's pattern (built on first use): per S block its value
+  // offset, the value offset of the same block in H, and its size
+  lsdm::i64 n_sblk = 0;
+  lsdm::DevBuf d_s2h_s, d_s2h_h, d_s2h_n;
+  bool s2h_ready = false;
+  std::mutex s2h_mutex;
+  lsdm::DevBuf wSh;                 // S on H's pattern (electron count)
   // optional kernel timing: event pairs around product launches
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;

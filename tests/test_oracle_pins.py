@@ -17,6 +17,7 @@ import scipy.sparse as sp
 import oracle
 import workloads
 from tests import _dense
+from tests._sides import onsite_values
 
 
 # ---------------------------------------------------------------------------
@@ -480,3 +481,105 @@ def test_generator_translation_invariance():
         key = s.sub[j[bs]] * 10**6 + (d[:, 0] + 50) * 10**4 + (d[:, 1] + 50) * 100 + d[:, 2] + 50
         rows.append(np.concatenate([M.block(b).ravel() for b in bs[np.argsort(key)]]))
     np.testing.assert_array_equal(rows[0], rows[1])
+
+
+# ---------------------------------------------------------------------------
+# minimisation of E over L: exact cubic line search and conjugate gradients
+# ---------------------------------------------------------------------------
+def test_line_coeffs_reproduce_energy_and_gradient():
+    """The expanded coefficients of E(L + tD) reproduce the literal energy at
+    arbitrary t (E is exactly cubic in t), for a non-symmetric direction too,
+    and c1 equals <dE/dL, D> from the independent gradient chain."""
+    s = workloads.config(1)["system"]
+    rS, rH, rL = 8.0, 12.0, 12.0
+    inp = _inputs(s, rS, rH, rL)
+    G = oracle.lnv_gradient(inp["L"], inp["S"], inp["H"], rS, rH, rL)
+    rng = np.random.default_rng(7)
+    for D in (oracle.Matrix(G.pattern, -G.val), oracle.Matrix(G.pattern, 0.05 * rng.normal(size=G.val.size))):
+        c = oracle.lnv_line_coeffs(inp["L"], D, inp["S"], inp["H"], rS, rH, rL)
+        for t in (0.37, -0.8, 1.3):
+            Lt = oracle.Matrix(inp["L"].pattern, inp["L"].val + t * D.val)
+            E = oracle.lnv_energy(Lt, inp["S"], inp["H"], rS, rH, rL, literal=True)["E"]
+            assert abs(E - (c[0] + c[1] * t + c[2] * t * t + c[3] * t ** 3)) <= 1e-12 * max(abs(E), 1.0)
+    Dsym = oracle.Matrix(G.pattern, -G.val)      # symmetric direction: the gradient formula applies
+    c = oracle.lnv_line_coeffs(inp["L"], Dsym, inp["S"], inp["H"], rS, rH, rL)
+    assert abs(c[1] - oracle.dot(G.val, Dsym.val)) <= 1e-12 * abs(c[1])
+
+
+def test_cubic_step_is_local_minimum():
+    for c in ([0.0, -3.0, 2.0, 0.5], [1.0, -1.0, 0.0, 1.0], [0.0, -2.0, 1.0, 0.0]):
+        t = oracle.cubic_step(c, 0.1)
+        assert t > 0
+        assert abs(c[1] + 2 * c[2] * t + 3 * c[3] * t * t) < 1e-12
+        assert 2 * c[2] + 6 * c[3] * t > 0
+    # a cubic with no local minimum along the line takes the trial step
+    assert oracle.cubic_step([0.0, -1.0, -1.0, -1.0], 0.25) == 0.25
+
+
+def onsite_minimiser_case():
+    """On-site-only system (ranges below the nearest-neighbour distance), S = I,
+    H_ii = Q_i diag(-1, -0.5, 0.3, 1) Q_i^T, L = I/2: the minimum of
+    2 Tr[(3L^2 - 2L^3) H] is the projector on H's negative eigenvectors,
+    E = 2 (-1.5) per atom."""
+    s = workloads.diamond(2, jitter=0.05, seed=2)
+    rS = rH = rL = 4.0
+    v = onsite_values(s.n)
+    pat = {k: oracle.pattern(s, r) for k, r in (("S", rS), ("H", rH), ("L", rL))}
+    for p in pat.values():
+        assert p.nblocks == s.n and np.all(p.col == np.arange(s.n))
+    S, H, L0 = (oracle.Matrix(pat[k], v[k].copy()) for k in "SHL")
+    return s, (rS, rH, rL), L0, S, H, v["P"], -3.0 * s.n
+
+
+def test_minimiser_closed_form_projector():
+    s, (rS, rH, rL), L0, S, H, P, Emin = onsite_minimiser_case()
+    Lf, Es, gs = oracle.lnv_minimise(L0, S, H, rS, rH, rL, max_iter=80, gtol=1e-11)
+    assert np.all(np.diff(Es) <= 1e-12 * abs(Emin))          # monotone descent
+    assert gs[-1] <= 1e-11
+    assert abs(Es[-1] - Emin) <= 1e-12 * abs(Emin)
+    np.testing.assert_allclose(Lf.val, P, atol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# electron number and chemical potential (constraint 2 of the ground-state search)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mixed", [False, True])
+def test_electron_number_vs_dense(mixed):
+    """N_e = 2 Tr(KS) with K = 3LSL - 2LSLSL untruncated (dense), and H - mu S
+    equals the dense H - mu S on H's pattern."""
+    s = _cluster(n=36, edge=13.0, mixed=mixed, seed=11)
+    rS, rH, rL = 4.0, 5.0, 5.5
+    inp = _inputs(s, rS, rH, rL)
+    L, S, H = (_dense.to_dense(inp[k]) for k in "LSH")
+    Kd = 3 * L @ S @ L - 2 * L @ S @ L @ S @ L
+    Nd = 2 * np.trace(Kd @ S)
+    N = oracle.electron_number(inp["L"], inp["S"], rS, rH, rL)
+    assert abs(N - Nd) <= 1e-13 * abs(Nd)
+    Hm = oracle.shift(inp["H"], inp["S"], 0.37)
+    np.testing.assert_array_equal(_dense.to_dense(Hm), (H - 0.37 * S) * _dense.mask_dense(inp["H"].pattern))
+    Ed = 2 * np.trace(Kd @ (H - 0.37 * S))
+    E = oracle.lnv_energy(inp["L"], inp["S"], Hm, rS, rH, rL)["E"]
+    assert abs(E - Ed) <= 1e-13 * max(abs(Ed), abs(Nd))
+
+
+def test_electron_number_closed_form():
+    """On-site blocks only, S = I, L = l I: K = (3 l^2 - 2 l^3) I, N_e = 2 (3 l^2 - 2 l^3) n_orb."""
+    s, (rS, rH, rL), _, S, H, P, _ = onsite_minimiser_case()
+    for l in (0.3, 0.5, 1.1):
+        L = oracle.Matrix(oracle.pattern(s, rL), np.tile(l * np.eye(4).ravel(), s.n))
+        N = oracle.electron_number(L, S, rS, rH, rL)
+        assert abs(N - 2 * (3 * l * l - 2 * l ** 3) * 4 * s.n) <= 1e-13 * 4 * s.n
+    # the projector on two of four functions per atom holds 4 electrons per atom
+    Lp = oracle.Matrix(oracle.pattern(s, rL), P)
+    assert abs(oracle.electron_number(Lp, S, rS, rH, rL) - 4.0 * s.n) <= 1e-12 * s.n
+
+
+def test_minimiser_grand_potential_closed_form():
+    """Minimising 2 Tr[K(H - mu S)] on the on-site case fills every level below
+    mu: with levels (-1, -0.5, 0.3, 1) and mu = 0.5, three per atom, so
+    E - mu N_e = 2 (-1.5 - 1.0 - 0.2) per atom and N_e = 6 per atom."""
+    s, (rS, rH, rL), L0, S, H, _, _ = onsite_minimiser_case()
+    Hm = oracle.shift(H, S, 0.5)
+    Lf, Es, gs = oracle.lnv_minimise(L0, S, Hm, rS, rH, rL, max_iter=80, gtol=1e-11)
+    assert abs(Es[-1] - (-5.4 * s.n)) <= 1e-12 * 5.4 * s.n
+    assert abs(oracle.electron_number(Lf, S, rS, rH, rL) - 6.0 * s.n) <= 1e-9 * s.n
