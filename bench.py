@@ -96,16 +96,23 @@ PRODUCT_KERNEL = {"fp64": "k_gprod<double>", "fp32": "k_gprod_rs<float>", "bf16"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_si32768.json")
 
 
+def workloads_default_name():
+    import workloads
+    return workloads.CONFIGS[4]["name"]
+
+
 def kernel_hash():
     import hashlib
     with open(KERNEL_SRC, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic_per_step(prec):
+def traffic_per_step(prec, workload):
     """HBM bytes (fetch + write) of one step's product launches, from the
-    committed counter summary when it was taken on the current kernel source
-    and the same precision; None otherwise."""
+    committed counter summary when it was taken on the current kernel source,
+    the same precision and the 32768-atom workload; None otherwise."""
+    if workload != workloads_default_name():
+        return None
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -251,18 +258,18 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": args.prec,
-        "data": "synthetic (seeded diamond-Si geometry and S/H/L value laws)",
+        "data": f"synthetic (seeded {sysm.name} geometry and S/H/L value laws)",
         "config": {"workload": cfg["name"], "atoms": sysm.n, "ranges_bohr": [cfg["rS"], cfg["rH"], cfg["rL"]],
-                   "fns_per_atom": "4" if args.config != 5 else "13/5", "flop_per_step": flops,
+                   "fns_per_atom": "/".join(str(int(k)) for k in sorted(set(sysm.nfn.tolist()), reverse=True)), "flop_per_step": flops,
                    "triples_per_step": n_triples, "symbolic_s": round(t_sym, 2), "parallelism": "single GPU"},
         "modes": {m: {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()} for m, r in res.items()},
         "roofline": {"kernel": f"{PRODUCT_KERNEL[args.prec]} (all 8 product launches of a step; traffic in "
                                f"HBM bytes per step)", "bound": "mfma",
                      "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": traffic_per_step(args.prec),
+                     "frac": round(achieved / peak, 4), "traffic": traffic_per_step(args.prec, cfg["name"]),
                      "per_product": per_product},
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.config == 4:
         out["cpu_baseline"] = cpu_baseline(cfg, flops / sysm.n)
     print(json.dumps(out), flush=True)
 

@@ -109,6 +109,7 @@ def fd_check(lnv, v, G, n_blocks=20, h=0.25, prec="fp64", seed=0, tol=1e-7):
 SMALL = {
     "config1_si64": lambda: (workloads.config(1)["system"], 8.0, 12.0, 12.0),
     "mixed_box_13_5": lambda: (workloads.random_box(300, 17.5, 240, 13, 5, seed=2), 6.0, 8.0, 8.0),
+    "si_slab_h_2x2x2": lambda: (workloads.si_slab((2, 2, 2)), 8.0, 12.0, 16.0),
 }
 # chain error allowances, relative: about ten times the observed error of a
 # five-product chain whose inputs are rounded with unit roundoff u
@@ -191,6 +192,32 @@ def test_config5_mixed_blocks_rows_and_fd():
     say("[config5] finite differences on 8 L blocks")
     fd_check(lnv, v, G, n_blocks=8, seed=5)
     Em, Gm = lnv.energy_grad(v["L"], v["S"], v["H"], prec="fp32")
+    eE = abs(Em.item() - E.item()) / abs(E.item())
+    say(f"    fp32: E rel err {eE:.3e} = {1e6 * abs(Em.item() - E.item()) / s.n:.4f} uHa/atom")
+    assert eE <= CHAIN_TOL["fp32"][0]
+
+
+def test_config6_slab_rows_and_fd():
+    """H-terminated (001) slab: surface and hydrogen rows have fewer neighbours
+    than bulk rows; K and dE/dL rows against the oracle at full size."""
+    c = workloads.config(6)
+    s = c["system"]
+    rS, rH, rL = c["rS"], c["rH"], c["rL"]
+    say(f"[config6] {s.n} atoms, slab with H: setup")
+    lnv, v = setup(s, rS, rH, rL)
+    E, K = lnv.energy(v["L"], v["S"], v["H"], want_K=True)
+    _, G = lnv.energy_grad(v["L"], v["S"], v["H"])
+    si = np.where(s.nfn == 4)[0]
+    h = np.where(s.nfn == 1)[0]
+    z = s.xyz[:, 2]
+    mid = si[np.argmin(np.abs(z[si] - np.median(z[si])))]
+    rows = np.array(sorted({int(si[np.argmax(z[si])]), int(mid), int(h[0]), int(h[-1])}))
+    grad_rows = np.array(sorted({int(si[np.argmin(z[si])]), int(h[7])}))
+    say(f"[config6] oracle rows {rows.tolist()} grad rows {grad_rows.tolist()}")
+    check_rows(lnv, s, v, rS, rH, rL, rows, grad_rows=grad_rows, K=K, G=G)
+    say("[config6] finite differences on 10 L blocks")
+    fd_check(lnv, v, G, n_blocks=10, seed=6)
+    Em, _ = lnv.energy_grad(v["L"], v["S"], v["H"], prec="fp32")
     eE = abs(Em.item() - E.item()) / abs(E.item())
     say(f"    fp32: E rel err {eE:.3e} = {1e6 * abs(Em.item() - E.item()) / s.n:.4f} uHa/atom")
     assert eE <= CHAIN_TOL["fp32"][0]

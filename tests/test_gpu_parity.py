@@ -142,6 +142,7 @@ CHAIN_CASES = {
     "si64_jitter_rl16": lambda: (workloads.diamond(2, jitter=0.1, seed=7), 8.0, 12.0, 16.0),
     "mixed_box_13_5": lambda: (workloads.random_box(300, 17.5, 240, 13, 5, seed=2), 6.0, 8.0, 8.0),
     "open_cluster_ragged": lambda: (workloads.random_cluster(90, 14.0, nfn=np.arange(90) % 5 + 1, seed=9), 5.0, 6.0, 6.5),
+    "si_slab_h_2x2x2": lambda: (workloads.si_slab((2, 2, 2)), 8.0, 12.0, 16.0),
 }
 
 

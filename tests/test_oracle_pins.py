@@ -466,6 +466,28 @@ def test_generator_symmetric_and_order_free(which, sysname):
         np.testing.assert_array_equal(M.block(b), expect)
 
 
+def test_slab_geometry():
+    """H-terminated (001) slab: 8 Si per cell, two H per surface Si on each face,
+    every Si four-fold bonded (Si at the bulk distance or H at 2.8 bohr), every
+    H bonded to one Si, and the vacuum wider than the longest range in use."""
+    nx, ny, nz = 2, 3, 2
+    s = workloads.si_slab((nx, ny, nz))
+    si, h = s.nfn == 4, s.nfn == 1
+    assert si.sum() == 8 * nx * ny * nz and h.sum() == 8 * nx * ny
+    a = 10.26
+    L = np.diag(s.lattice)
+    d = s.xyz[:, None, :] - s.xyz[None, :, :]
+    d[..., :2] -= np.round(d[..., :2] / L[:2]) * L[:2]          # periodic in x and y only
+    r = np.sqrt((d * d).sum(-1))
+    bulk = np.sqrt(3.0) * a / 4
+    nsi = ((np.abs(r - bulk) < 1e-9) & si[None, :]).sum(1)
+    nh = ((np.abs(r - 2.8) < 1e-9) & h[None, :]).sum(1)
+    assert np.all(nsi[si] + nh[si] == 4)
+    assert np.all(((np.abs(r - 2.8) < 1e-9) & si[None, :]).sum(1)[h] == 1)
+    gap = L[2] - np.ptp(s.xyz[:, 2])
+    assert gap >= 2 * 16.0 + 8.0                                  # 2 R_L + R_S of the slab workload
+
+
 def test_generator_translation_invariance():
     s = workloads.diamond(2)
     p = oracle.pattern(s, 12.0)

@@ -33,6 +33,7 @@ SYSTEMS = {
     "si8_cell": lambda: workloads.diamond(1),
     "mixed_box": lambda: workloads.random_box(120, 14.0, 96, 13, 5, seed=3),
     "open_mixed": lambda: workloads.random_cluster(50, 12.0, nfn=np.arange(50) % 7 + 1, seed=4),
+    "si_slab_h": lambda: workloads.si_slab((2, 1, 1)),
 }
 
 
@@ -47,7 +48,7 @@ def test_pattern_equals_oracle(name, R):
     assert same_pattern(gp, op)
 
 
-@pytest.mark.parametrize("name", ["si64", "mixed_box", "open_mixed"])
+@pytest.mark.parametrize("name", ["si64", "mixed_box", "open_mixed", "si_slab_h"])
 @pytest.mark.parametrize("tA,tB", [(0, 0), (1, 0), (0, 1)])
 def test_plan_triples_equal_oracle(name, tA, tB):
     s = SYSTEMS[name]()

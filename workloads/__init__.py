@@ -109,6 +109,39 @@ def random_cluster(n_atoms: int, edge: float, nfn=4, seed: int = 0) -> System:
                   name=f"cluster{n_atoms}")
 
 
+def si_slab(ncell, a: float = 10.26, vacuum: float = 45.0, bond_h: float = 2.8, nfn_si: int = 4,
+            nfn_h: int = 1) -> System:
+    """Hydrogen-terminated (001) slab of diamond silicon: ncell = (nx, ny, nz)
+    conventional cells, periodic in x and y, `vacuum` bohr of empty space along
+    z, and one H atom (nfn_h functions) on every broken bond, `bond_h` bohr from
+    its Si along the bulk bond direction.  Atoms near the surfaces have fewer
+    neighbours within a range than bulk atoms."""
+    nx, ny, nz = (int(v) for v in ncell)
+    c = np.stack(np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij"), -1).reshape(-1, 3)
+    cell = np.repeat(c, 8, axis=0).astype(np.int64)
+    sub = np.tile(np.arange(8), c.shape[0]).astype(np.int64)
+    si = (cell + DIAMOND_BASIS[sub]) * a
+    # bulk bonds: from an fcc site along (1,1,1) and the vectors with two signs
+    # flipped; from a shifted site along their negatives
+    bonds = 0.25 * a * np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], dtype=np.float64)
+    top = nz * a
+    hs = []
+    for k in range(4):
+        v = np.where((sub < 4)[:, None], bonds[k][None, :], -bonds[k][None, :])
+        zn = si[:, 2] + v[:, 2]
+        broken = (zn < -1e-9) | (zn > top - 0.25 * a + 1e-9)
+        hs.append(si[broken] + (bond_h / np.sqrt(3.0) / (0.25 * a)) * v[broken])
+    h = np.concatenate(hs)
+    xyz = np.concatenate([si, h])
+    xyz[:, 2] += 0.5 * vacuum                     # slab in the middle of the cell along z
+    xyz[:, 0] = np.mod(xyz[:, 0], nx * a)
+    xyz[:, 1] = np.mod(xyz[:, 1], ny * a)
+    nfn = np.concatenate([np.full(si.shape[0], nfn_si, np.int32), np.full(h.shape[0], nfn_h, np.int32)])
+    lattice = np.diag([nx * a, ny * a, nz * a + vacuum]).astype(np.float64)
+    return System(xyz=np.ascontiguousarray(xyz), nfn=nfn, lattice=lattice, key_mode="pair",
+                  name=f"si001slab{nx}x{ny}x{nz}_h")
+
+
 # ---------------------------------------------------------------------------
 # workloads: the five synthetic configurations (sizes from the paper's Table 1
 # rows where they match: 4,096 and 32,768 atoms)
@@ -128,6 +161,10 @@ CONFIGS = {
             make=lambda seed=0: diamond(16, seed=seed)),
     5: dict(name="mixed8000_rl14", atoms=8000, rS=10.0, rH=14.0, rL=14.0,
             make=lambda seed=0: random_box(8000, _cfg5_edge(), 6400, 13, 5, seed=seed)),
+    # surface-terminated, non-cubic cell: 16 x 16 x 8 conventional cells of Si
+    # (16,384 atoms) with 2,048 H on the two (001) faces and 45 bohr of vacuum
+    6: dict(name="si001slab18432_h_rl16", atoms=18432, rS=8.0, rH=12.0, rL=16.0,
+            make=lambda seed=0: si_slab((16, 16, 8))),
 }
 
 
