@@ -517,7 +517,6 @@ __global__ void __launch_bounds__(256) k_gprod_rs(const GTile* __restrict__ tile
   const int a_off = (4 * wave + ai) * 16 + (TA ? (kk * 4 + ar) : (ar * 4 + kk));
   const int b_off = ((lane & 15) >> 2) * 16 + kk * 4 + (lane & 3);
   const int abit = 4 * wave + ai;
-  constexpr uint32_t COL = 1u | (1u << GJ) | (1u << (2 * GJ)) | (1u << (3 * GJ));
   // contiguous tile ranges per XCD (workgroups are dealt to the 8 XCDs round
   // robin), so concurrent tiles of one XCD share A and B through its L2
   const i64 xcd = blockIdx.x & 7, nbx = gridDim.x >> 3, lb = blockIdx.x >> 3;
@@ -601,19 +600,22 @@ __global__ void __launch_bounds__(256) k_gprod_rs(const GTile* __restrict__ tile
         if (more_d) load_operands((q + 1) % 3, dn);
         const int rs = q % 3, ds = q & 1;
         const int nv = ns - SB * q;
-        // slot masks of this wavefront (lane r < SB) and row bits (lane SB + r)
-        // of the batch's steps, read once per batch
+        // per step of the batch, read once per batch: lane r < SB holds the
+        // column quads with an active slot in this wavefront's rows (the OR of
+        // the four rows' GJ-bit fields, 0 past the tile's end), lane SB + r the
+        // row bits; one bit test per column quad then decides each MFMA
         int mr = 0;
-        if (lane < SB)
-          mr = rbuf[rs][lane * RW + GROWS + GJ + wave];
-        else if (lane < 2 * SB)
+        if (lane < SB) {
+          const uint32_t m = (uint32_t)rbuf[rs][lane * RW + GROWS + GJ + wave];
+          mr = lane < nv ? (int)((m | (m >> GJ) | (m >> (2 * GJ)) | (m >> (3 * GJ))) & ((1u << GJ) - 1u)) : 0;
+        } else if (lane < 2 * SB) {
           mr = rbuf[rs][(lane - SB) * RW + GROWS + GJ + GQ];
+        }
 #pragma unroll 1
         for (int r = 0; r < SB; ++r) {
-          uint32_t mask = (uint32_t)__builtin_amdgcn_readlane(mr, r);
+          const uint32_t jm = (uint32_t)__builtin_amdgcn_readlane(mr, r);
+          if (jm == 0u) continue;
           const uint32_t rows = (uint32_t)__builtin_amdgcn_readlane(mr, SB + r);
-          if (r >= nv) mask = 0u;
-          if (mask == 0u) continue;
           const T* sA = &dbuf[ds][r * SV];
           T av = sA[a_off];
           av = ((rows >> abit) & 1u) ? av : (T)0;
@@ -622,7 +624,7 @@ __global__ void __launch_bounds__(256) k_gprod_rs(const GTile* __restrict__ tile
           for (int j = 0; j < GJ; ++j) bv[j] = sA[AV + j * 64 + b_off];
 #pragma unroll
           for (int j = 0; j < GJ; ++j)
-            if ((mask >> j) & COL) acc[j] = Mma16<T>::mma(av, bv[j], acc[j]);
+            if (jm & (1u << j)) acc[j] = Mma16<T>::mma(av, bv[j], acc[j]);
         }
         if (more_d) store_operands(dn, (q + 1) & 1);
         if (more_r) store_records(rn, (q + 2) % 3);
