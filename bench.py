@@ -7,10 +7,15 @@ and the five adjoint products giving dE/dL, all in the library's kernels.
 Default workload: diamond Si 16x16x16 cells (32,768 atoms), S/H/L ranges
 8/12/16 bohr, 4 functions per atom, seeded synthetic S, H, L.
 
+By default the chain runs in symmetric mode (L, S and H are symmetric, so
+M, P and dE/dL are computed on one half and mirrored); --full times the chain
+without that, and the JSON line also carries the FP32 step time of the full
+chain for comparison.
+
 Prints one JSON line (rank 0, N = 1).  The value is useful GFLOP/s of the
-primary precision (useful = 2 nfn_i nfn_k nfn_j per block triple of the
-truncated products).  Extra modes are reported with their energy error per
-atom against the FP64 result.
+primary precision (useful = 2 nfn_i nfn_k nfn_j per block triple that the
+step's products compute).  Extra modes are reported with their energy error
+per atom against the FP64 result.
 """
 import argparse
 import json
@@ -182,6 +187,8 @@ def main():
     ap.add_argument("--modes", default="fp64,fp32,bf16,fp32_rc", help="modes to time; fp64 is the error reference")
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--full", action="store_true", help="no symmetric mode (every product computes all its strips)")
+    ap.add_argument("--no-full-compare", action="store_true", help="skip the FP32 timing of the full chain")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (reference dispatch for HBM counters)")
     args = ap.parse_args()
@@ -200,7 +207,8 @@ def main():
     sysm = cfg["system"]
     t0 = time.perf_counter()
     gs = lsdm.System.from_workload(sysm)
-    lnv = lsdm.LNV(gs, cfg["rS"], cfg["rH"], cfg["rL"])
+    symmetric = not args.full
+    lnv = lsdm.LNV(gs, cfg["rS"], cfg["rH"], cfg["rL"], symmetric=symmetric)
     t_sym = time.perf_counter() - t0
     n_triples, flops = lnv.info(True)
     log(f"[bench] config {args.config} {cfg['name']}: {sysm.n} atoms, symbolic {t_sym:.1f} s, "
@@ -230,6 +238,16 @@ def main():
     if "fp64" in res:
         for m in res:
             res[m]["err_uHa_per_atom"] = 1e6 * abs(res[m]["E"] - res["fp64"]["E"]) / sysm.n
+
+    full_cmp = None
+    if symmetric and not args.no_full_compare and args.profile_steps > 0:
+        full = lsdm.LNV(gs, cfg["rS"], cfg["rH"], cfg["rL"])
+        ms_full, E_full, _ = time_mode(full, inp, "fp32", args.steps, args.warmup)
+        full_cmp = {"ms_per_step": round(ms_full, 4), "flop_per_step": full.info(True)[1],
+                    "E": E_full}
+        log(f"[bench] full chain fp32: {ms_full:.3f} ms/step")
+        del full
+        torch.cuda.empty_cache()
 
     prim = res[args.prec]
     if args.profile_steps <= 0:
@@ -261,7 +279,8 @@ def main():
         "data": f"synthetic (seeded {sysm.name} geometry and S/H/L value laws)",
         "config": {"workload": cfg["name"], "atoms": sysm.n, "ranges_bohr": [cfg["rS"], cfg["rH"], cfg["rL"]],
                    "fns_per_atom": "/".join(str(int(k)) for k in sorted(set(sysm.nfn.tolist()), reverse=True)), "flop_per_step": flops,
-                   "triples_per_step": n_triples, "symbolic_s": round(t_sym, 2), "parallelism": "single GPU"},
+                   "triples_per_step": n_triples, "symbolic_s": round(t_sym, 2), "symmetric": symmetric,
+                   "parallelism": "single GPU"},
         "modes": {m: {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()} for m, r in res.items()},
         "roofline": {"kernel": f"{PRODUCT_KERNEL[args.prec]} (all 8 product launches of a step; traffic in "
                                f"HBM bytes per step)", "bound": "mfma",
@@ -269,6 +288,8 @@ def main():
                      "frac": round(achieved / peak, 4), "traffic": traffic_per_step(args.prec, cfg["name"]),
                      "per_product": per_product},
     }
+    if full_cmp is not None:
+        out["full_chain_fp32"] = full_cmp
     if not args.no_cpu_baseline and args.config == 4:
         out["cpu_baseline"] = cpu_baseline(cfg, flops / sysm.n)
     print(json.dumps(out), flush=True)

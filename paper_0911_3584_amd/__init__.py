@@ -164,9 +164,15 @@ class LNV:
 
     NAMES = ("S", "H", "L", "X", "M")
 
-    def __init__(self, system, rS, rH, rL):
+    SYMMETRIC = 1
+
+    def __init__(self, system, rS, rH, rL, symmetric=False):
+        """symmetric=True: L, S and H are symmetric (every L passed later too);
+        M, P and dE/dL are then computed on one half and mirrored."""
         h = ctypes.c_void_p()
-        check(lib().lsdm_lnv_create(system._h, float(rS), float(rH), float(rL), ctypes.byref(h)))
+        check(lib().lsdm_lnv_create_ex(system._h, float(rS), float(rH), float(rL),
+                                       self.SYMMETRIC if symmetric else 0, ctypes.byref(h)))
+        self.symmetric = bool(symmetric)
         self._h = h
         self._destroy = lib().lsdm_lnv_destroy
         self.system = system

@@ -101,7 +101,8 @@ static lsdm_pattern* make_pattern(const lsdm_system* sys, double R) {
   return p.release();
 }
 
-static lsdm_plan* make_plan(const lsdm_pattern* A, int tA, const lsdm_pattern* B, int tB, const lsdm_pattern* C) {
+static lsdm_plan* make_plan(const lsdm_pattern* A, int tA, const lsdm_pattern* B, int tB, const lsdm_pattern* C,
+                            bool half = false) {
   if (!A || !B || !C) LSDM_THROW(LSDM_EINVAL, "null pattern");
   if (A->sys != B->sys || A->sys != C->sys) LSDM_THROW(LSDM_EPATTERN, "patterns belong to different systems");
   std::unique_ptr<lsdm_plan> pl(new lsdm_plan());
@@ -110,6 +111,7 @@ static lsdm_plan* make_plan(const lsdm_pattern* A, int tA, const lsdm_pattern* B
   pl->C = C;
   pl->transA = tA ? 1 : 0;
   pl->transB = tB ? 1 : 0;
+  pl->half = half ? 1 : 0;
   build_plan(pl.get());
   return pl.release();
 }
@@ -221,13 +223,16 @@ static void lnv_build(lsdm_lnv* L) {
   L->pX = make_pattern(L->sys, rX);
   L->pM = make_pattern(L->sys, rM);
   L->F1 = make_plan(L->pL, 0, L->pS, 0, L->pX);
-  L->F2 = make_plan(L->pX, 0, L->pL, 0, L->pM);
-  L->F3 = make_plan(L->pX, 0, L->pM, 0, L->pH);
+  // symmetric mode: M = LSL, P = LSLSL and dE/dL are symmetric, so their
+  // products (F2, F3, and B4 + B5, whose sum is dE/dL) fill one half
+  const bool h = L->sym;
+  L->F2 = make_plan(L->pX, 0, L->pL, 0, L->pM, h);
+  L->F3 = make_plan(L->pX, 0, L->pM, 0, L->pH, h);
   L->B1 = make_plan(L->pX, 1, L->pH, 0, L->pM);
   L->B2 = make_plan(L->pH, 0, L->pM, 0, L->pX);
   L->B3 = make_plan(L->pM, 0, L->pL, 0, L->pX);
-  L->B4 = make_plan(L->pX, 1, L->pM, 0, L->pL);
-  L->B5 = make_plan(L->pX, 0, L->pS, 0, L->pL);
+  L->B4 = make_plan(L->pX, 1, L->pM, 0, L->pL, h);
+  L->B5 = make_plan(L->pX, 0, L->pS, 0, L->pL, h);
   // H strip -> M strip with the same (row, column quad, image); M's range
   // contains H's, so every H strip has one
   const lsdm_pattern* H = L->pH;
@@ -305,7 +310,9 @@ static void lnv_forward(lsdm_lnv* L, const double* dL, const double* dS, const d
   user_to_strip<double>(L->pH, dH, wH64, 1.0, st);
   chain_product<T>(L, 0, wL, wS, wX, 1.0, 0.0, st);     // X = LS
   chain_product<T>(L, 1, wX, wL, wM, 1.0, 0.0, st);     // M = XL
+  if (L->sym) sym_fill<T>(L->pM, wM, st);
   chain_product<T>(L, 2, wX, wM, wP, 1.0, 0.0, st);     // P = XM on H's range
+  if (L->sym) sym_fill<T>(L->pH, wP, st);
   kassembly<T>(L, wM, wP, wK, st);                  // K = 3 M|_H - 2 P
   dot(wK, wH64, L->pH->n_strips * 64, 2.0, L->wE.as<double>(), dE, st);   // E = 2 <K, H>
   if (dK) strip_to_user<double>(L->pH, wK, dK, st);
@@ -329,6 +336,7 @@ static void lnv_backward(lsdm_lnv* L, double* dG, hipStream_t st) {
   chain_product<T>(L, 5, wMb, wL, wXb, 1.0, 1.0, st);    // Xbar += Mbar L
   chain_product<T>(L, 6, wX, wMb, wLb, 1.0, 0.0, st);    // Lbar  = X^T Mbar
   chain_product<T>(L, 7, wXb, wS, wLb, 1.0, 1.0, st);    // Lbar += Xbar S
+  if (L->sym) sym_fill<T>(L->pL, wLb, st);
   strip_to_user<T>(L->pL, wLb, dG, st);
   check_launch();
 }
@@ -389,8 +397,10 @@ static void lnv_forward_bf16(lsdm_lnv* L, const double* dL, const double* dS, co
   chain_product_bf16(L, 0, h(LR), h(SC), wX, 1.0, 0.0, st);    // X = LS
   to_bf16(wX, h(XR), h(XC), L->pX->n_strips * 64, st);
   chain_product_bf16(L, 1, h(XR), h(LC), wM, 1.0, 0.0, st);    // M = XL
+  if (L->sym) sym_fill<float>(L->pM, wM, st);
   to_bf16(wM, nullptr, h(MC), L->pM->n_strips * 64, st);
   chain_product_bf16(L, 2, h(XR), h(MC), wP, 1.0, 0.0, st);    // P = XM on H's range
+  if (L->sym) sym_fill<float>(L->pH, wP, st);
   kassembly<float>(L, wM, wP, wK, st);
   dot(wK, wH64, L->pH->n_strips * 64, 2.0, L->wE.as<double>(), dE, st);
   if (dK) strip_to_user<double>(L->pH, wK, dK, st);
@@ -413,6 +423,7 @@ static void lnv_backward_bf16(lsdm_lnv* L, double* dG, hipStream_t st) {
   to_bf16(wXb, h(XbR), nullptr, L->pX->n_strips * 64, st);
   chain_product_bf16(L, 6, h(XC), h(MbC), wLb, 1.0, 0.0, st);   // Lbar = X^T Mbar
   chain_product_bf16(L, 7, h(XbR), h(SC), wLb, 1.0, 1.0, st);   // Lbar += Xbar S
+  if (L->sym) sym_fill<float>(L->pL, wLb, st);
   strip_to_user<float>(L->pL, wLb, dG, st);
   check_launch();
 }
@@ -460,8 +471,10 @@ static void lnv_forward_rc(lsdm_lnv* L, const double* dL, const double* dS, cons
   rc_step(L, 0, wL, r(RL), wS, r(RS), wX, 1.0, 0.0, st);       // X = LS
   offsite_f32(L->pX, wX, r(RX), st);
   rc_step(L, 1, wX, r(RX), wL, r(RL), wM, 1.0, 0.0, st);       // M = XL
+  if (L->sym) sym_fill<double>(L->pM, wM, st);
   offsite_f32(L->pM, wM, r(RM), st);
   rc_step(L, 2, wX, r(RX), wM, r(RM), wP, 1.0, 0.0, st);       // P = XM on H's range
+  if (L->sym) sym_fill<double>(L->pH, wP, st);
   kassembly<double>(L, wM, wP, wK, st);
   dot(wK, wH, L->pH->n_strips * 64, 2.0, L->wE.as<double>(), dE, st);
   if (dK) strip_to_user<double>(L->pH, wK, dK, st);
@@ -487,6 +500,7 @@ static void lnv_backward_rc(lsdm_lnv* L, double* dG, hipStream_t st) {
   offsite_f32(L->pX, wXb, r(RXb), st);
   rc_step(L, 6, wX, r(RX), wMb, r(RMb), wLb, 1.0, 0.0, st);    // Lbar = X^T Mbar
   rc_step(L, 7, wXb, r(RXb), wS, r(RS), wLb, 1.0, 1.0, st);    // Lbar += Xbar S
+  if (L->sym) sym_fill<double>(L->pL, wLb, st);
   strip_to_user<double>(L->pL, wLb, dG, st);
   check_launch();
 }
@@ -644,9 +658,14 @@ int lsdm_dot(const lsdm_pattern* p, const double* dA, const double* dB, double* 
 }
 
 int lsdm_lnv_create(const lsdm_system* sys, double rS, double rH, double rL, lsdm_lnv** out) {
+  return lsdm_lnv_create_ex(sys, rS, rH, rL, 0, out);
+}
+
+int lsdm_lnv_create_ex(const lsdm_system* sys, double rS, double rH, double rL, int flags, lsdm_lnv** out) {
   return guarded([&] {
     if (!sys || !out) LSDM_THROW(LSDM_EINVAL, "null argument");
     *out = nullptr;
+    if (flags & ~LSDM_LNV_SYMMETRIC) LSDM_THROW(LSDM_EINVAL, "unknown flag");
     for (double r : {rS, rH, rL})
       if (!(r >= 0.0) || !std::isfinite(r)) LSDM_THROW(LSDM_EINVAL, "ranges must be finite and >= 0");
     std::unique_ptr<lsdm_lnv> L(new lsdm_lnv());
@@ -654,6 +673,7 @@ int lsdm_lnv_create(const lsdm_system* sys, double rS, double rH, double rL, lsd
     L->rS = rS;
     L->rH = rH;
     L->rL = rL;
+    L->sym = (flags & LSDM_LNV_SYMMETRIC) != 0;
     try {
       lnv_build(L.get());
     } catch (...) {

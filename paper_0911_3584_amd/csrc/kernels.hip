@@ -74,6 +74,27 @@ __global__ void k_transpose_strips(const T* __restrict__ in, T* __restrict__ out
   }
 }
 
+// The dropped half of a symmetric result from its kept half, in place: one
+// thread per row of a block to fill (the list holds strip << 4 | block mask),
+// which gathers the matching column of the mirror block.  The mirror of a
+// filled block is never filled itself: blocks outside keep_strip mirror into
+// kept strips, and in a row's own quad at image 0 the blocks below the
+// diagonal mirror to blocks above it.  Absent blocks of a filled strip are
+// written as zero.
+template <class T>
+__global__ void k_sym_fill(T* data, const i64* __restrict__ fill, const i64* __restrict__ mirror, i64 nfill) {
+  for (i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x; g < nfill * 16; g += (i64)gridDim.x * blockDim.x) {
+    const i64 e = fill[g >> 4];
+    const int t = (int)((g >> 2) & 3), r = (int)(g & 3);
+    if (!((e >> t) & 1)) continue;
+    const i64 s = e >> 4;
+    const i64 m = mirror[4 * s + t];
+    T* dst = data + s * 64 + t * 16 + r * 4;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) dst[c] = m < 0 ? (T)0 : data[m + c * 4 + r];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Dense 16x16x4 MFMA forms used by the product kernels: one instruction per
 // active column quad covers the 4 rows of a row quad at once.
@@ -1079,6 +1100,16 @@ void transpose_strips(const lsdm_pattern* p, const T* in, T* out, hipStream_t st
 }
 template void transpose_strips<double>(const lsdm_pattern*, const double*, double*, hipStream_t);
 template void transpose_strips<float>(const lsdm_pattern*, const float*, float*, hipStream_t);
+
+template <class T>
+void sym_fill(const lsdm_pattern* p, T* data, hipStream_t st) {
+  ensure_maps(const_cast<lsdm_pattern*>(p));
+  if (p->n_fill == 0) return;
+  hipLaunchKernelGGL(k_sym_fill<T>, dim3(grid_for(p->n_fill * 16)), dim3(256), 0, st, data, p->d_fill.as<i64>(),
+                     p->d_mirror.as<i64>(), p->n_fill);
+}
+template void sym_fill<double>(const lsdm_pattern*, double*, hipStream_t);
+template void sym_fill<float>(const lsdm_pattern*, float*, hipStream_t);
 
 // Grid of the group kernel: as many workgroups as are resident at once (so
 // every workgroup of an XCD walks its tile range in step with the others), a

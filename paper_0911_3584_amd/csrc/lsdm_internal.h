@@ -68,6 +68,13 @@ __host__ __device__ inline i32 img_neg(i32 a) {
 constexpr i32 IMG0 = (128 << 16) | (128 << 8) | 128;
 // strip key: column quad and image in one sortable 64-bit value
 __host__ __device__ inline i64 skey(i32 quad, i32 img) { return ((i64)quad << 24) | (i64)img; }
+// Half of a symmetric matrix that a half-output product computes: strips
+// whose column quad lies above the row's quad, and the row's own quad at
+// images >= 0.  The other strips are mirrors of these: block (p, q, n) of a
+// dropped strip is the transpose of (q, p, -n), which lies in a kept strip.
+__host__ __device__ inline bool keep_strip(i32 row, i32 quad, i32 img) {
+  return quad > (row >> 2) || (quad == (row >> 2) && img >= IMG0);
+}
 
 }  // namespace lsdm
 
@@ -120,7 +127,12 @@ struct lsdm_pattern {
   // mirror map for transposes in strip layout: for strip s of row p, the
   // strip index of (q, quad(p), -n) for each of its 4 blocks q
   lsdm::DevBuf d_mirror;            // i64[4 * n_strips], -1 when absent
-  bool maps_ready = false;          // the three maps above are built on first use
+  // blocks that a symmetric result takes from their mirrors: strip index << 4
+  // | mask of its blocks to fill (strips outside keep_strip, and the blocks
+  // below the diagonal in a row's own quad at image 0)
+  lsdm::i64 n_fill = 0;
+  lsdm::DevBuf d_fill;
+  bool maps_ready = false;          // the maps above are built on first use
   std::mutex maps_mutex;
 };
 
@@ -170,6 +182,7 @@ struct lsdm_plan {
   const lsdm_pattern* B = nullptr;
   const lsdm_pattern* C = nullptr;
   int transA = 0, transB = 0;
+  int half = 0;                     // output restricted to keep_strip (symmetric result)
   lsdm::i64 n_triples = 0;
   double flops = 0;
   // group tiles and their steps
@@ -190,6 +203,9 @@ struct lsdm_plan {
 struct lsdm_lnv {
   const lsdm_system* sys = nullptr;
   double rS = 0, rH = 0, rL = 0;
+  // symmetric mode: L, S, H are symmetric, so M, P and dE/dL are computed on
+  // one half (F2, F3, B4, B5 half-output plans) and mirrored
+  bool sym = false;
   lsdm_pattern *pS = nullptr, *pH = nullptr, *pL = nullptr, *pX = nullptr, *pM = nullptr;
   lsdm_plan *F1 = nullptr, *F2 = nullptr, *F3 = nullptr;
   lsdm_plan *B1 = nullptr, *B2 = nullptr, *B3 = nullptr, *B4 = nullptr, *B5 = nullptr;

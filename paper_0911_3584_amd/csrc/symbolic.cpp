@@ -375,6 +375,21 @@ void ensure_maps(lsdm_pattern* p) {
       }
   });
   p->d_mirror.upload(mir.data(), sizeof(i64) * mir.size());
+  std::vector<i64> fl;
+  for (i32 q = 0; q < np; ++q)
+    for (i64 st = p->sptr[q]; st < p->sptr[q + 1]; ++st) {
+      int m = 0;
+      if (!keep_strip(q, p->squad[st], p->simg[st])) {
+        m = 15;                       // every block: absent ones are written as zero
+      } else if (p->squad[st] == (q >> 2) && p->simg[st] == IMG0) {
+        for (int t = 0; t < 4; ++t)
+          if (4 * p->squad[st] + t < q) m |= 1 << t;
+        m &= p->smask[st];
+      }
+      if (m) fl.push_back((st << 4) | m);
+    }
+  p->n_fill = (i64)fl.size();
+  p->d_fill.upload(fl.data(), sizeof(i64) * fl.size());
   p->maps_ready = true;
 }
 
@@ -429,13 +444,15 @@ static void inner_list(const lsdm_pattern* A, bool tA, i32 row0, std::vector<Ent
   }
 }
 
-// sorted, distinct column keys of C's strips in rows row0 .. row0+nr-1
-static std::vector<i64> column_keys(const lsdm_pattern* C, i32 row0, int nr) {
+// sorted, distinct column keys of C's strips in rows row0 .. row0+nr-1 (only
+// the kept half when `half`)
+static std::vector<i64> column_keys(const lsdm_pattern* C, i32 row0, int nr, bool half) {
   std::vector<i64> ck;
   for (int ii = 0; ii < nr; ++ii) {
     const i32 row = row0 + ii;
     if (row >= C->sys->n_pseudo) break;
-    for (i64 st = C->sptr[row]; st < C->sptr[row + 1]; ++st) ck.push_back(skey(C->squad[st], C->simg[st]));
+    for (i64 st = C->sptr[row]; st < C->sptr[row + 1]; ++st)
+      if (!half || keep_strip(row, C->squad[st], C->simg[st])) ck.push_back(skey(C->squad[st], C->simg[st]));
   }
   std::sort(ck.begin(), ck.end());
   ck.erase(std::unique(ck.begin(), ck.end()), ck.end());
@@ -457,7 +474,8 @@ void build_plan(lsdm_plan* pl) {
   parallel_for(ng, [&](i64 g) {
     const i32 row0 = GROWS * (i32)g;
     inner_list<GROWS>(A, tA, row0, kents[g]);
-    const std::vector<i64> ckeys = column_keys(C, row0, GROWS);
+    const bool half = pl->half != 0;
+    const std::vector<i64> ckeys = column_keys(C, row0, GROWS, half);
     const i64 nt = ((i64)ckeys.size() + GJ - 1) / GJ;
     std::vector<GTile> T(nt);
     for (i64 t = 0; t < nt; ++t) {
@@ -470,6 +488,7 @@ void build_plan(lsdm_plan* pl) {
       const i32 row = row0 + r;
       if (row >= s->n_pseudo) break;
       for (i64 st = C->sptr[row]; st < C->sptr[row + 1]; ++st) {
+        if (half && !keep_strip(row, C->squad[st], C->simg[st])) continue;
         const i64 c = std::lower_bound(ckeys.begin(), ckeys.end(), skey(C->squad[st], C->simg[st])) - ckeys.begin();
         T[c / GJ].cstrip[GJ * r + (c % GJ)] = (i32)st;
       }

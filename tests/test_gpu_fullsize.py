@@ -36,8 +36,8 @@ def T(x):
     return torch.from_numpy(np.ascontiguousarray(x, np.float64)).to(DEV)
 
 
-def setup(s, rS, rH, rL):
-    lnv = lsdm.LNV(lsdm.System.from_workload(s), rS, rH, rL)
+def setup(s, rS, rH, rL, symmetric=False):
+    lnv = lsdm.LNV(lsdm.System.from_workload(s), rS, rH, rL, symmetric=symmetric)
     v = {w: T(gpu_values(lnv.patterns[w], s, w, rS=rS)) for w in "LSH"}
     return lnv, v
 
@@ -118,12 +118,13 @@ SMALL = {
 CHAIN_TOL = {"fp32": (1e-5, 1e-4), "bf16": (3e-2, 1.5e-1), "fp32_rc": (1e-8, 1e-6)}
 
 
+@pytest.mark.parametrize("symmetric", [False, True], ids=["full", "sym"])
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp32_rc"])
 @pytest.mark.parametrize("name", list(SMALL))
-def test_lnv_reduced_precision(prec, name):
+def test_lnv_reduced_precision(prec, name, symmetric):
     s, rS, rH, rL = SMALL[name]()
-    say(f"[reduced] {name} {prec}")
-    lnv, v = setup(s, rS, rH, rL)
+    say(f"[reduced] {name} {prec} symmetric={symmetric}")
+    lnv, v = setup(s, rS, rH, rL, symmetric=symmetric)
     inp = oracle.make_inputs(s, rS, rH, rL)
     ref = oracle.lnv_energy(inp["L"], inp["S"], inp["H"], rS, rH, rL)
     Gref = oracle.lnv_gradient(inp["L"], inp["S"], inp["H"], rS, rH, rL)
@@ -156,12 +157,13 @@ def test_config3_jitter_fp64_rows_and_fd():
     say(f"    worst FD relative deviation {worst:.2e}")
 
 
-def test_config4_extensive_energy_rows_and_modes():
+@pytest.mark.parametrize("symmetric", [False, True], ids=["full", "sym"])
+def test_config4_extensive_energy_rows_and_modes(symmetric):
     c = workloads.config(4)
     s = c["system"]
     rS, rH, rL = c["rS"], c["rH"], c["rL"]
-    say(f"[config4] {s.n} atoms, RL16: setup")
-    lnv, v = setup(s, rS, rH, rL)
+    say(f"[config4] {s.n} atoms, RL16, symmetric={symmetric}: setup")
+    lnv, v = setup(s, rS, rH, rL, symmetric=symmetric)
     E, K = lnv.energy(v["L"], v["S"], v["H"], want_K=True)
     _, G = lnv.energy_grad(v["L"], v["S"], v["H"])
     # translation-class values make E extensive: the 64-atom cell fixes E/N

@@ -130,3 +130,13 @@ def test_minimise_onsite_closed_form():
     assert abs(Es[-1] + 5.4 * s.n) <= 1e-10 * 5.4 * s.n
     assert np.all(np.diff(Es) <= 1e-12 * 5.4 * s.n)
     assert abs(lnv.electrons(L, S).item() - 6.0 * s.n) <= 1e-5 * s.n
+
+
+def test_minimise_symmetric_mode_matches():
+    s, (rS, rH, rL), lnv, v, inp = _config1()
+    sym = lsdm.LNV(lsdm.System.from_workload(s), rS, rH, rL, symmetric=True)
+    Hm = lnv.shift(T(v["S"]), T(v["H"]), mu=1.0)
+    E1, g1 = lnv.minimise(T(v["L"]).clone(), T(v["S"]), Hm, max_iter=6, gtol=0.0)
+    E2, g2 = sym.minimise(T(v["L"]).clone(), T(v["S"]), sym.shift(T(v["S"]), T(v["H"]), mu=1.0), max_iter=6, gtol=0.0)
+    np.testing.assert_allclose(E2, E1, rtol=1e-10)
+    np.testing.assert_allclose(g2, g1, rtol=1e-6)

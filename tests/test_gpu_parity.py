@@ -128,9 +128,9 @@ def test_product_adjoint_and_dot():
 # ---------------------------------------------------------------------------
 # the LNV chain
 # ---------------------------------------------------------------------------
-def _chain_setup(s, rS, rH, rL, seed=0):
+def _chain_setup(s, rS, rH, rL, seed=0, symmetric=False):
     gs = lsdm.System.from_workload(s)
-    lnv = lsdm.LNV(gs, rS, rH, rL)
+    lnv = lsdm.LNV(gs, rS, rH, rL, symmetric=symmetric)
     p = lnv.patterns
     vals = {w: gpu_values(p[w], s, w, seed=seed, rS=rS) for w in "LSH"}
     return lnv, vals
@@ -146,11 +146,12 @@ CHAIN_CASES = {
 }
 
 
+@pytest.mark.parametrize("symmetric", [False, True], ids=["full", "sym"])
 @pytest.mark.parametrize("name", list(CHAIN_CASES))
-def test_lnv_energy_grad_fp64(name):
+def test_lnv_energy_grad_fp64(name, symmetric):
     s, rS, rH, rL = CHAIN_CASES[name]()
-    say(f"[lnv fp64] {name} atoms={s.n}")
-    lnv, v = _chain_setup(s, rS, rH, rL)
+    say(f"[lnv fp64] {name} atoms={s.n} symmetric={symmetric}")
+    lnv, v = _chain_setup(s, rS, rH, rL, symmetric=symmetric)
     inp = oracle.make_inputs(s, rS, rH, rL)
     for w in "LSH":
         assert same_pattern(lnv.patterns[w], inp[w].pattern)
@@ -206,3 +207,38 @@ def test_autograd_function():
     (3.0 * E).backward()
     _, G = lnv.energy_grad(T(v["L"]), T(v["S"]), T(v["H"]))
     assert torch.equal(L.grad, 3.0 * G)
+
+
+def test_symmetric_mode_flops_and_agreement():
+    """The symmetric handle does fewer flops and agrees with the full one; its
+    K and dE/dL are exactly symmetric (mirrored halves)."""
+    s, rS, rH, rL = CHAIN_CASES["si64_jitter_rl16"]()
+    full, v = _chain_setup(s, rS, rH, rL)
+    sym, _ = _chain_setup(s, rS, rH, rL, symmetric=True)
+    assert sym.info(True)[1] < 0.8 * full.info(True)[1]
+    inp = oracle.make_inputs(s, rS, rH, rL)
+    for prec in ("fp64", "fp32", "bf16", "fp32_rc"):
+        E1, G1 = full.energy_grad(T(v["L"]), T(v["S"]), T(v["H"]), prec=prec)
+        E2, G2 = sym.energy_grad(T(v["L"]), T(v["S"]), T(v["H"]), prec=prec)
+        # the two handles differ by the rounding of each mode (the mirrored
+        # half is computed as the transposed product)
+        tE, tG = {"fp64": (1e-13, 1e-12), "fp32": (1e-6, 1e-5), "bf16": (1e-2, 1e-1),
+                  "fp32_rc": (1e-11, 1e-7)}[prec]
+        assert abs(E1.item() - E2.item()) <= tE * abs(E1.item()), (prec, E1.item(), E2.item())
+        assert rel(G2.cpu().numpy(), G1.cpu().numpy()) <= tG, prec
+        _assert_mirrored(G2.cpu().numpy(), inp["L"].pattern, tG)
+    _, K = sym.energy(T(v["L"]), T(v["S"]), T(v["H"]), want_K=True)
+    _assert_mirrored(K.cpu().numpy(), inp["H"].pattern)
+
+
+def _assert_mirrored(vals, pat, tol=1e-12):
+    """Off-site blocks equal their mirrors' transposes exactly; on-site blocks,
+    computed whole, are symmetric up to rounding."""
+    t = oracle.transpose(oracle.Matrix(pat, vals), pat).val
+    rows = pat.rows_of_blocks()
+    onsite = np.zeros(vals.size, bool)
+    for b in np.where((pat.col == rows) & np.all(np.asarray(pat.img).reshape(-1, 3) == 0, axis=1))[0]:
+        n = int(np.sqrt(pat.off[b + 1] - pat.off[b])) if b + 1 < pat.nblocks else int(np.sqrt(pat.nval - pat.off[b]))
+        onsite[pat.off[b]:pat.off[b] + n * n] = True
+    np.testing.assert_array_equal(vals[~onsite], t[~onsite])
+    np.testing.assert_allclose(vals[onsite], t[onsite], rtol=0, atol=tol * np.abs(vals).max())
