@@ -9,3 +9,24 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: takes more than a few seconds on the CPU")
+
+
+import gc  # noqa: E402
+
+import pytest  # noqa: E402
+
+
+@pytest.fixture(autouse=True)
+def _release_device_memory(request):
+    """Library handles of one test are freed before the next: an LNV handle and
+    its borrowed patterns reference each other, so only the cyclic collector
+    frees them, and the full-size handles hold tens of GB of plans and
+    workspaces."""
+    yield
+    if request.node.get_closest_marker("gpu") is None:
+        return
+    gc.collect()
+    torch = sys.modules.get("torch")
+    if torch is not None and torch.cuda.is_available():
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
