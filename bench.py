@@ -89,10 +89,16 @@ def cpu_baseline(cfg, flops_per_atom):
     oracle.lnv_gradient(inp["L"], inp["S"], inp["H"], rS, rH, rL)
     dt = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": round(flops_per_atom * s.n / dt / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"FP64 oracle E + dE/dL of the 13824-atom 12x12x12 periodic cell at the same ranges "
                       f"({dt:.2f} s; same per-atom work as the full cell), equivalent useful GFLOP/s",
-            "seconds": round(dt, 3), "energy_per_atom": r["E"] / s.n}
+            "seconds": round(dt, 3), "energy_per_atom": r["E"] / s.n, "cpu_model": model}
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_0911_3584_amd", "csrc", "kernels.hip")

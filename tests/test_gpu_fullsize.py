@@ -181,6 +181,21 @@ def test_config4_extensive_energy_rows_and_modes(symmetric):
         assert eE <= CHAIN_TOL[prec][0] and eG <= CHAIN_TOL[prec][1]
 
 
+def test_config4_pair_keys_rows():
+    """The 32,768-atom cell with per-pair value keys (no translation symmetry in
+    the values): K and dE/dL rows against the oracle's dependency cones, in
+    symmetric mode (the bench's default)."""
+    c = workloads.config(4)
+    s = workloads.diamond(16, key_mode="pair")
+    rS, rH, rL = c["rS"], c["rH"], c["rL"]
+    say(f"[config4 pair keys] {s.n} atoms: setup")
+    lnv, v = setup(s, rS, rH, rL, symmetric=True)
+    E, K = lnv.energy(v["L"], v["S"], v["H"], want_K=True)
+    _, G = lnv.energy_grad(v["L"], v["S"], v["H"])
+    say("[config4 pair keys] oracle rows")
+    check_rows(lnv, s, v, rS, rH, rL, np.array([1, 16383, 32766]), grad_rows=np.array([777, 31000]), K=K, G=G)
+
+
 def test_config5_mixed_blocks_rows_and_fd():
     c = workloads.config(5)
     s = c["system"]

@@ -1,8 +1,9 @@
 """GPU parity: the HIP path against the FP64 oracle on the same seeded inputs.
 
 FP64 bar (stated target): relative error <= 1e-12 for E, and in Frobenius norm
-for every product, K and dE/dL.  FP32 products are held to the a-priori bound
-of the FP32 rounding of inputs and accumulation (see test_gpu_precision.py).
+for every product, K and dE/dL.  FP32, BF16 and FP32-residual products are
+held to the a-priori bound of the rounding of inputs and accumulation
+(test_product_parity); whole chains in those modes are in test_gpu_fullsize.py.
 """
 import sys
 
@@ -166,10 +167,13 @@ def test_lnv_energy_grad_fp64(name, symmetric):
     assert rel(G.cpu().numpy(), G_ref.val) <= TOL64, rel(G.cpu().numpy(), G_ref.val)
 
 
-def test_lnv_config2_fp64():
+@pytest.mark.parametrize("key_mode", ["class", "pair"])
+def test_lnv_config2_fp64(key_mode):
+    """4,096 atoms; with per-pair value keys as well, so that no translation
+    symmetry of the values can hide a block read from the wrong place."""
     c = workloads.config(2)
-    s = c["system"]
-    say(f"[lnv fp64] config2 atoms={s.n}")
+    s = c["system"] if key_mode == "class" else workloads.diamond(8, key_mode="pair")
+    say(f"[lnv fp64] config2 atoms={s.n} keys={key_mode}")
     lnv, v = _chain_setup(s, c["rS"], c["rH"], c["rL"])
     inp = oracle.make_inputs(s, c["rS"], c["rH"], c["rL"])
     for w in "LSH":

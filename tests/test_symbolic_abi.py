@@ -117,6 +117,14 @@ def test_errors():
     with pytest.raises(lsdm.LsdmError) as e:
         lsdm.System(s.xyz, s.nfn, sing)
     assert e.value.code == lsdm._lib.EINVAL
+    h = ctypes.c_void_p()
+    rc = lsdm.lib().lsdm_lnv_create_ex(gs._h, 4.0, 5.0, 5.0, 2, ctypes.byref(h))
+    assert rc == lsdm._lib.EINVAL and not h.value
+    # symmetric-mode plans: fewer triples than the full chain, same patterns
+    full, sym = lsdm.LNV(gs, 4.0, 6.0, 6.0), lsdm.LNV(gs, 4.0, 6.0, 6.0, symmetric=True)
+    assert sym.info(True)[0] < full.info(True)[0] and sym.info(False)[0] < full.info(False)[0]
+    for w in full.patterns:
+        assert full.patterns[w].n_values == sym.patterns[w].n_values
 
 
 def test_compute_without_device_fails_loudly():
