@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "fp32_rc": 157.3}   # MI355X dense matrix peaks
 HBM_PEAK_GBS = 8000.0
+DEFAULT_WORKLOAD = "si32768_rl16"    # diamond Si 16x16x16 cells, ranges 8/12/16 bohr
 
 
 def log(*a):
@@ -109,7 +110,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_si32768.json")
 
 def workloads_default_name():
     import workloads
-    return workloads.CONFIGS[4]["name"]
+    return DEFAULT_WORKLOAD
 
 
 def kernel_hash():
@@ -188,7 +189,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=4)
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, help="workload name (workloads.WORKLOADS)")
     ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16", "fp32_rc"])
     ap.add_argument("--modes", default="fp64,fp32,bf16,fp32_rc", help="modes to time; fp64 is the error reference")
     ap.add_argument("--profile-steps", type=int, default=3)
@@ -209,7 +210,7 @@ def main():
     import paper_0911_3584_amd as lsdm
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
-    cfg = workloads.config(args.config)
+    cfg = workloads.workload(args.workload)
     sysm = cfg["system"]
     t0 = time.perf_counter()
     gs = lsdm.System.from_workload(sysm)
@@ -217,7 +218,7 @@ def main():
     lnv = lsdm.LNV(gs, cfg["rS"], cfg["rH"], cfg["rL"], symmetric=symmetric)
     t_sym = time.perf_counter() - t0
     n_triples, flops = lnv.info(True)
-    log(f"[bench] config {args.config} {cfg['name']}: {sysm.n} atoms, symbolic {t_sym:.1f} s, "
+    log(f"[bench] {cfg['name']}: {sysm.n} atoms, symbolic {t_sym:.1f} s, "
         f"{n_triples / sysm.n:.0f} triples/atom, {flops:.3e} flop/step")
     t0 = time.perf_counter()
     inp = make_inputs(lnv, sysm, cfg["rS"], "cuda:0")
@@ -296,7 +297,7 @@ def main():
     }
     if full_cmp is not None:
         out["full_chain_fp32"] = full_cmp
-    if not args.no_cpu_baseline and args.config == 4:
+    if not args.no_cpu_baseline and args.workload == DEFAULT_WORKLOAD:
         out["cpu_baseline"] = cpu_baseline(cfg, flops / sysm.n)
     print(json.dumps(out), flush=True)
 

@@ -107,7 +107,7 @@ def fd_check(lnv, v, G, n_blocks=20, h=0.25, prec="fp64", seed=0, tol=1e-7):
 # reduced precision on small chains
 # ---------------------------------------------------------------------------
 SMALL = {
-    "config1_si64": lambda: (workloads.config(1)["system"], 8.0, 12.0, 12.0),
+    "si64_rl12": lambda: (workloads.workload("si64_rl12")["system"], 8.0, 12.0, 12.0),
     "mixed_box_13_5": lambda: (workloads.random_box(300, 17.5, 240, 13, 5, seed=2), 6.0, 8.0, 8.0),
     "si_slab_h_2x2x2": lambda: (workloads.si_slab((2, 2, 2)), 8.0, 12.0, 16.0),
 }
@@ -138,31 +138,31 @@ def test_lnv_reduced_precision(prec, name, symmetric):
 # ---------------------------------------------------------------------------
 # full sizes
 # ---------------------------------------------------------------------------
-def test_config3_jitter_fp64_rows_and_fd():
-    c = workloads.config(3)
+def test_si13824_jitter_fp64_rows_and_fd():
+    c = workloads.workload("si13824_jitter_rl16")
     s = c["system"]
     rS, rH, rL = c["rS"], c["rH"], c["rL"]
-    say(f"[config3] {s.n} atoms, jittered, RL16: setup")
+    say(f"[si13824] {s.n} atoms, jittered, RL16: setup")
     lnv, v = setup(s, rS, rH, rL)
     E, K = lnv.energy(v["L"], v["S"], v["H"], want_K=True)
     _, G = lnv.energy_grad(v["L"], v["S"], v["H"])
-    say("[config3] oracle rows")
+    say("[si13824] oracle rows")
     rows = np.array([0, 6911, 13823])
     check_rows(lnv, s, v, rS, rH, rL, rows, grad_rows=np.array([5000]), K=K, G=G)
     # E equals the sum of the per-row contributions 2 <K_i, H_i> (FP64 on the host)
     Hh = v["H"].cpu().numpy()
     assert abs(float(np.sum(K.cpu().numpy() * Hh)) * 2 - E.item()) <= 1e-12 * abs(E.item())
-    say("[config3] finite differences on 20 L blocks")
+    say("[si13824] finite differences on 20 L blocks")
     worst = fd_check(lnv, v, G, n_blocks=20)
     say(f"    worst FD relative deviation {worst:.2e}")
 
 
 @pytest.mark.parametrize("symmetric", [False, True], ids=["full", "sym"])
-def test_config4_extensive_energy_rows_and_modes(symmetric):
-    c = workloads.config(4)
+def test_si32768_extensive_energy_rows_and_modes(symmetric):
+    c = workloads.workload("si32768_rl16")
     s = c["system"]
     rS, rH, rL = c["rS"], c["rH"], c["rL"]
-    say(f"[config4] {s.n} atoms, RL16, symmetric={symmetric}: setup")
+    say(f"[si32768] {s.n} atoms, RL16, symmetric={symmetric}: setup")
     lnv, v = setup(s, rS, rH, rL, symmetric=symmetric)
     E, K = lnv.energy(v["L"], v["S"], v["H"], want_K=True)
     _, G = lnv.energy_grad(v["L"], v["S"], v["H"])
@@ -171,7 +171,7 @@ def test_config4_extensive_energy_rows_and_modes(symmetric):
     inp = oracle.make_inputs(small, rS, rH, rL)
     e_small = oracle.lnv_energy(inp["L"], inp["S"], inp["H"], rS, rH, rL)["E"] / small.n
     assert abs(E.item() / s.n - e_small) <= 1e-12 * abs(e_small), (E.item() / s.n, e_small)
-    say("[config4] oracle rows")
+    say("[si32768] oracle rows")
     check_rows(lnv, s, v, rS, rH, rL, np.array([0, 12345, 32767]), grad_rows=np.array([20000]), K=K, G=G)
     for prec in ("fp32", "bf16", "fp32_rc"):
         Em, Gm = lnv.energy_grad(v["L"], v["S"], v["H"], prec=prec)
@@ -181,32 +181,32 @@ def test_config4_extensive_energy_rows_and_modes(symmetric):
         assert eE <= CHAIN_TOL[prec][0] and eG <= CHAIN_TOL[prec][1]
 
 
-def test_config4_pair_keys_rows():
+def test_si32768_pair_keys_rows():
     """The 32,768-atom cell with per-pair value keys (no translation symmetry in
     the values): K and dE/dL rows against the oracle's dependency cones, in
     symmetric mode (the bench's default)."""
-    c = workloads.config(4)
+    c = workloads.workload("si32768_rl16")
     s = workloads.diamond(16, key_mode="pair")
     rS, rH, rL = c["rS"], c["rH"], c["rL"]
-    say(f"[config4 pair keys] {s.n} atoms: setup")
+    say(f"[si32768 pair keys] {s.n} atoms: setup")
     lnv, v = setup(s, rS, rH, rL, symmetric=True)
     E, K = lnv.energy(v["L"], v["S"], v["H"], want_K=True)
     _, G = lnv.energy_grad(v["L"], v["S"], v["H"])
-    say("[config4 pair keys] oracle rows")
+    say("[si32768 pair keys] oracle rows")
     check_rows(lnv, s, v, rS, rH, rL, np.array([1, 16383, 32766]), grad_rows=np.array([777, 31000]), K=K, G=G)
 
 
-def test_config5_mixed_blocks_rows_and_fd():
-    c = workloads.config(5)
+def test_mixed8000_blocks_rows_and_fd():
+    c = workloads.workload("mixed8000_rl14")
     s = c["system"]
     rS, rH, rL = c["rS"], c["rH"], c["rL"]
-    say(f"[config5] {s.n} atoms, 13/5 functions: setup")
+    say(f"[mixed8000] {s.n} atoms, 13/5 functions: setup")
     lnv, v = setup(s, rS, rH, rL)
     E, K = lnv.energy(v["L"], v["S"], v["H"], want_K=True)
     _, G = lnv.energy_grad(v["L"], v["S"], v["H"])
-    say("[config5] oracle rows")
+    say("[mixed8000] oracle rows")
     check_rows(lnv, s, v, rS, rH, rL, np.array([0, 4000, 7999]), K=K)
-    say("[config5] finite differences on 8 L blocks")
+    say("[mixed8000] finite differences on 8 L blocks")
     fd_check(lnv, v, G, n_blocks=8, seed=5)
     Em, Gm = lnv.energy_grad(v["L"], v["S"], v["H"], prec="fp32")
     eE = abs(Em.item() - E.item()) / abs(E.item())
@@ -214,13 +214,13 @@ def test_config5_mixed_blocks_rows_and_fd():
     assert eE <= CHAIN_TOL["fp32"][0]
 
 
-def test_config6_slab_rows_and_fd():
+def test_slab18432_rows_and_fd():
     """H-terminated (001) slab: surface and hydrogen rows have fewer neighbours
     than bulk rows; K and dE/dL rows against the oracle at full size."""
-    c = workloads.config(6)
+    c = workloads.workload("si001slab18432_h_rl16")
     s = c["system"]
     rS, rH, rL = c["rS"], c["rH"], c["rL"]
-    say(f"[config6] {s.n} atoms, slab with H: setup")
+    say(f"[slab18432] {s.n} atoms, slab with H: setup")
     lnv, v = setup(s, rS, rH, rL)
     E, K = lnv.energy(v["L"], v["S"], v["H"], want_K=True)
     _, G = lnv.energy_grad(v["L"], v["S"], v["H"])
@@ -230,9 +230,9 @@ def test_config6_slab_rows_and_fd():
     mid = si[np.argmin(np.abs(z[si] - np.median(z[si])))]
     rows = np.array(sorted({int(si[np.argmax(z[si])]), int(mid), int(h[0]), int(h[-1])}))
     grad_rows = np.array(sorted({int(si[np.argmin(z[si])]), int(h[7])}))
-    say(f"[config6] oracle rows {rows.tolist()} grad rows {grad_rows.tolist()}")
+    say(f"[slab18432] oracle rows {rows.tolist()} grad rows {grad_rows.tolist()}")
     check_rows(lnv, s, v, rS, rH, rL, rows, grad_rows=grad_rows, K=K, G=G)
-    say("[config6] finite differences on 10 L blocks")
+    say("[slab18432] finite differences on 10 L blocks")
     fd_check(lnv, v, G, n_blocks=10, seed=6)
     Em, _ = lnv.energy_grad(v["L"], v["S"], v["H"], prec="fp32")
     eE = abs(Em.item() - E.item()) / abs(E.item())

@@ -39,8 +39,8 @@ def T(x):
     return torch.from_numpy(np.ascontiguousarray(x, np.float64)).to(DEV)
 
 
-def _config1():
-    c = workloads.config(1)
+def _si64():
+    c = workloads.workload("si64_rl12")
     s, rS, rH, rL = c["system"], c["rS"], c["rH"], c["rL"]
     lnv = lsdm.LNV(lsdm.System.from_workload(s), rS, rH, rL)
     v = {w: gpu_values(lnv.patterns[w], s, w, rS=rS) for w in "LSH"}
@@ -52,8 +52,8 @@ def _config1():
 
 
 def test_shift_and_electron_number():
-    s, (rS, rH, rL), lnv, v, inp = _config1()
-    say(f"[shift/electrons] config1 atoms={s.n}")
+    s, (rS, rH, rL), lnv, v, inp = _si64()
+    say(f"[shift/electrons] si64 atoms={s.n}")
     Hm_ref = oracle.shift(inp["H"], inp["S"], 1.0)
     Hm = lnv.shift(T(v["S"]), T(v["H"]), mu=1.0).cpu().numpy()
     np.testing.assert_allclose(Hm, Hm_ref.val, rtol=0, atol=2.3e-16 * np.abs(v["S"]).max())
@@ -70,8 +70,8 @@ def test_shift_and_electron_number():
 
 @pytest.mark.parametrize("h", [1.0, 0.25])
 def test_line_coefficients(h):
-    s, (rS, rH, rL), lnv, v, inp = _config1()
-    say(f"[line] config1 h={h}")
+    s, (rS, rH, rL), lnv, v, inp = _si64()
+    say(f"[line] si64 h={h}")
     pL = inp["L"].pattern
     D = 0.05 * workloads.fd_direction(pL.nval, seed=3)          # no symmetry imposed
     c_ref = oracle.lnv_line_coeffs(inp["L"], oracle.Matrix(pL, D), inp["S"], inp["H"], rS, rH, rL)
@@ -81,9 +81,9 @@ def test_line_coefficients(h):
         assert abs(c[k] - c_ref[k]) * h ** k <= 1e-11 * scale, (k, c, c_ref)
 
 
-def test_minimise_grand_potential_config1():
-    s, (rS, rH, rL), lnv, v, inp = _config1()
-    say(f"[minimise fp64] config1 mu=1")
+def test_minimise_grand_potential_si64():
+    s, (rS, rH, rL), lnv, v, inp = _si64()
+    say(f"[minimise fp64] si64 mu=1")
     Hm = lnv.shift(T(v["S"]), T(v["H"]), mu=1.0)
     L = T(v["L"]).clone()
     Es, gs = lnv.minimise(L, T(v["S"]), Hm, max_iter=8, gtol=0.0)
@@ -102,7 +102,7 @@ def test_minimise_reduced_precision_tracks_fp64(prec):
     """Other precision modes run the same search; their energies stay within the
     modes' own error of the FP64 path (energy errors near 1e-7 relative on
     this cell)."""
-    s, (rS, rH, rL), lnv, v, inp = _config1()
+    s, (rS, rH, rL), lnv, v, inp = _si64()
     Hm = lnv.shift(T(v["S"]), T(v["H"]), mu=1.0)
     E64, _ = lnv.minimise(T(v["L"]).clone(), T(v["S"]), Hm, max_iter=6, gtol=0.0)
     E, _ = lnv.minimise(T(v["L"]).clone(), T(v["S"]), Hm, max_iter=6, gtol=0.0, prec=prec)
@@ -133,7 +133,7 @@ def test_minimise_onsite_closed_form():
 
 
 def test_minimise_symmetric_mode_matches():
-    s, (rS, rH, rL), lnv, v, inp = _config1()
+    s, (rS, rH, rL), lnv, v, inp = _si64()
     sym = lsdm.LNV(lsdm.System.from_workload(s), rS, rH, rL, symmetric=True)
     Hm = lnv.shift(T(v["S"]), T(v["H"]), mu=1.0)
     E1, g1 = lnv.minimise(T(v["L"]).clone(), T(v["S"]), Hm, max_iter=6, gtol=0.0)

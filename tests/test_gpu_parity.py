@@ -138,7 +138,7 @@ def _chain_setup(s, rS, rH, rL, seed=0, symmetric=False):
 
 
 CHAIN_CASES = {
-    "config1_si64": lambda: (workloads.config(1)["system"], 8.0, 12.0, 12.0),
+    "si64_rl12": lambda: (workloads.workload("si64_rl12")["system"], 8.0, 12.0, 12.0),
     "si8_cell_images": lambda: (workloads.diamond(1), 8.0, 12.0, 12.0),
     "si64_jitter_rl16": lambda: (workloads.diamond(2, jitter=0.1, seed=7), 8.0, 12.0, 16.0),
     "mixed_box_13_5": lambda: (workloads.random_box(300, 17.5, 240, 13, 5, seed=2), 6.0, 8.0, 8.0),
@@ -168,12 +168,12 @@ def test_lnv_energy_grad_fp64(name, symmetric):
 
 
 @pytest.mark.parametrize("key_mode", ["class", "pair"])
-def test_lnv_config2_fp64(key_mode):
+def test_lnv_si4096_fp64(key_mode):
     """4,096 atoms; with per-pair value keys as well, so that no translation
     symmetry of the values can hide a block read from the wrong place."""
-    c = workloads.config(2)
+    c = workloads.workload("si4096_rl12")
     s = c["system"] if key_mode == "class" else workloads.diamond(8, key_mode="pair")
-    say(f"[lnv fp64] config2 atoms={s.n} keys={key_mode}")
+    say(f"[lnv fp64] si4096 atoms={s.n} keys={key_mode}")
     lnv, v = _chain_setup(s, c["rS"], c["rH"], c["rL"])
     inp = oracle.make_inputs(s, c["rS"], c["rH"], c["rL"])
     for w in "LSH":

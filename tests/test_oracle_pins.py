@@ -174,7 +174,7 @@ def test_chain_vs_dense(mixed):
 
 
 def test_k_symmetry_and_associativity():
-    c = workloads.config(1)
+    c = workloads.workload("si64_rl12")
     s = c["system"]
     inp = _inputs(s, c["rS"], c["rH"], c["rL"])
     r = oracle.lnv_energy(inp["L"], inp["S"], inp["H"], c["rS"], c["rH"], c["rL"])
@@ -384,7 +384,7 @@ def test_gradient_vs_dense_formula_open():
 # row cones: single rows of a large system match the full computation
 # ---------------------------------------------------------------------------
 def test_row_cones_match_full():
-    c = workloads.config(1)
+    c = workloads.workload("si64_rl12")
     s = workloads.diamond(2, jitter=0.1, seed=1)
     rS, rH, rL = c["rS"], c["rH"], c["rL"]
     inp = _inputs(s, rS, rH, rL)
@@ -512,7 +512,7 @@ def test_line_coeffs_reproduce_energy_and_gradient():
     """The expanded coefficients of E(L + tD) reproduce the literal energy at
     arbitrary t (E is exactly cubic in t), for a non-symmetric direction too,
     and c1 equals <dE/dL, D> from the independent gradient chain."""
-    s = workloads.config(1)["system"]
+    s = workloads.workload("si64_rl12")["system"]
     rS, rH, rL = 8.0, 12.0, 12.0
     inp = _inputs(s, rS, rH, rL)
     G = oracle.lnv_gradient(inp["L"], inp["S"], inp["H"], rS, rH, rL)

@@ -77,7 +77,7 @@ def test_plan_triples_equal_oracle(name, tA, tB):
     assert plan.flops == fl
 
 
-def test_lnv_work_counts_config1():
+def test_lnv_work_counts_si64():
     """Useful triples per atom of the chain on perfect diamond Si, RL = 12:
     forward X, LSL, LSLSL and the five adjoint products."""
     s = workloads.diamond(2)

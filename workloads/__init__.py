@@ -146,30 +146,32 @@ def si_slab(ncell, a: float = 10.26, vacuum: float = 45.0, bond_h: float = 2.8, 
 # workloads: the five synthetic configurations (sizes from the paper's Table 1
 # rows where they match: 4,096 and 32,768 atoms)
 # ---------------------------------------------------------------------------
-def _cfg5_edge(n=8000, density_per_A3=0.05):
+def _mixed_box_edge(n=8000, density_per_A3=0.05):
     return (n / density_per_A3) ** (1.0 / 3.0) * BOHR_PER_ANGSTROM
 
 
-CONFIGS = {
-    1: dict(name="si64_rl12", atoms=64, rS=8.0, rH=12.0, rL=12.0,
-            make=lambda seed=0: diamond(2, seed=seed)),
-    2: dict(name="si4096_rl12", atoms=4096, rS=8.0, rH=12.0, rL=12.0,
-            make=lambda seed=0: diamond(8, seed=seed)),
-    3: dict(name="si13824_jitter_rl16", atoms=13824, rS=8.0, rH=12.0, rL=16.0,
-            make=lambda seed=0: diamond(12, jitter=0.1, seed=seed)),
-    4: dict(name="si32768_rl16", atoms=32768, rS=8.0, rH=12.0, rL=16.0,
-            make=lambda seed=0: diamond(16, seed=seed)),
-    5: dict(name="mixed8000_rl14", atoms=8000, rS=10.0, rH=14.0, rL=14.0,
-            make=lambda seed=0: random_box(8000, _cfg5_edge(), 6400, 13, 5, seed=seed)),
+WORKLOADS = {
+    "si64_rl12": dict(atoms=64, rS=8.0, rH=12.0, rL=12.0,
+         make=lambda seed=0: diamond(2, seed=seed)),
+    "si4096_rl12": dict(atoms=4096, rS=8.0, rH=12.0, rL=12.0,
+         make=lambda seed=0: diamond(8, seed=seed)),
+    "si13824_jitter_rl16": dict(atoms=13824, rS=8.0, rH=12.0, rL=16.0,
+         make=lambda seed=0: diamond(12, jitter=0.1, seed=seed)),
+    "si32768_rl16": dict(atoms=32768, rS=8.0, rH=12.0, rL=16.0,
+         make=lambda seed=0: diamond(16, seed=seed)),
+    "mixed8000_rl14": dict(atoms=8000, rS=10.0, rH=14.0, rL=14.0,
+         make=lambda seed=0: random_box(8000, _mixed_box_edge(), 6400, 13, 5, seed=seed)),
     # surface-terminated, non-cubic cell: 16 x 16 x 8 conventional cells of Si
     # (16,384 atoms) with 2,048 H on the two (001) faces and 45 bohr of vacuum
-    6: dict(name="si001slab18432_h_rl16", atoms=18432, rS=8.0, rH=12.0, rL=16.0,
-            make=lambda seed=0: si_slab((16, 16, 8))),
+    "si001slab18432_h_rl16": dict(atoms=18432, rS=8.0, rH=12.0, rL=16.0,
+         make=lambda seed=0: si_slab((16, 16, 8))),
 }
 
 
-def config(k: int, seed: int = 0):
-    c = dict(CONFIGS[k])
+def workload(name: str, seed: int = 0):
+    """The named workload: its system, ranges and size, as a dict."""
+    c = dict(WORKLOADS[name])
+    c["name"] = name
     c["system"] = c.pop("make")(seed)
     return c
 
