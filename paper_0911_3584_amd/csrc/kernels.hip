@@ -74,6 +74,14 @@ __global__ void k_transpose_strips(const T* __restrict__ in, T* __restrict__ out
   }
 }
 
+__device__ __forceinline__ void store4(float* p, const float (&v)[4]) {
+  *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void store4(double* p, const double (&v)[4]) {
+  reinterpret_cast<double2*>(p)[0] = make_double2(v[0], v[1]);
+  reinterpret_cast<double2*>(p)[1] = make_double2(v[2], v[3]);
+}
+
 // The dropped half of a symmetric result from its kept half, in place: one
 // thread per row of a block to fill (the list holds strip << 4 | block mask),
 // which gathers the matching column of the mirror block.  The mirror of a
@@ -89,9 +97,10 @@ __global__ void k_sym_fill(T* data, const i64* __restrict__ fill, const i64* __r
     if (!((e >> t) & 1)) continue;
     const i64 s = e >> 4;
     const i64 m = mirror[4 * s + t];
-    T* dst = data + s * 64 + t * 16 + r * 4;
+    T v[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) dst[c] = m < 0 ? (T)0 : data[m + c * 4 + r];
+    for (int c = 0; c < 4; ++c) v[c] = m < 0 ? (T)0 : data[m + c * 4 + r];
+    store4(data + s * 64 + t * 16 + r * 4, v);   // one 16- or 32-byte store
   }
 }
 
