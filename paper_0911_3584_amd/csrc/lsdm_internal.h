@@ -4,7 +4,7 @@
 // at most 4 support functions (an atom with nfn = 13 becomes 4 pseudo-atoms,
 // the last padded with 3 zero rows/columns), so all internal blocks are 4x4
 // and match the 4x4x4 multi-block MFMA forms of gfx950.  Atoms are ordered
-// along a Morton curve so that consecutive pseudo-atoms are spatially close;
+// along a Hilbert curve so that consecutive pseudo-atoms are spatially close;
 // a "quad" is 4 consecutive pseudo-atoms.  A matrix row (one pseudo-atom) is
 // stored as a list of strips, one per column quad (and lattice image) that
 // holds at least one in-range pair: 4 blocks of 4x4 = 64 values, block t for
@@ -86,7 +86,7 @@ struct lsdm_system {
   std::vector<lsdm::i32> nfn;       // user order
   bool periodic = false;
   double lat[9] = {0}, inv[9] = {0};
-  // Morton ordering and pseudo-atoms
+  // Hilbert ordering and pseudo-atoms
   std::vector<lsdm::i32> order;     // internal atom position -> user atom
   std::vector<lsdm::i32> pbase;     // user atom -> first pseudo-atom
   std::vector<lsdm::i32> npseudo;   // user atom -> number of pseudo-atoms

@@ -4,11 +4,12 @@
 //
 // Source of the operations: Bowler & Miyazaki, section 2.  A range pattern is
 // the set of atom pairs within the cutoff (stated after eq. 3); a truncated
-// product keeps only the output blocks of its own range pattern.  The
-// partition/bundle ordering of the paper's parallel scheme (Hilbert curves) is
-// replaced here by a Morton ordering of atoms, used only so that consecutive
-// pseudo-atoms are close in space and 4x4 block groups of the MFMA kernels
-// share neighbours.
+// product keeps only the output blocks of its own range pattern.  Atoms are
+// ordered along a Hilbert curve, as the paper's partitioner orders atoms into
+// partitions (Results, strong scaling); here the order serves the MFMA
+// kernels: consecutive pseudo-atoms are close in space, so the 4x4 block
+// groups (quads) and the 16-atom row groups of a tile are compact and share
+// neighbours.
 #include <algorithm>
 #include <array>
 #include <atomic>
@@ -68,8 +69,36 @@ static uint64_t spread3(uint64_t v) {  // 21 bits -> every third bit
   return v;
 }
 
+// Position of the point (x0, x1, x2) (each `bits` bits) along a 3-D Hilbert
+// curve, by Skilling's transform of the coordinates into the transposed
+// Hilbert index (J. Skilling, "Programming the Hilbert curve", AIP Conf. Proc.
+// 707, 2004), whose bits are then interleaved, x0's first.
+static uint64_t hilbert3(uint64_t x0, uint64_t x1, uint64_t x2, int bits) {
+  uint64_t X[3] = {x0, x1, x2};
+  const uint64_t M = (uint64_t)1 << (bits - 1);
+  for (uint64_t Q = M; Q > 1; Q >>= 1) {           // undo the excess work of the inverse
+    const uint64_t P = Q - 1;
+    for (int i = 0; i < 3; ++i) {
+      if (X[i] & Q) {
+        X[0] ^= P;
+      } else {
+        const uint64_t t = (X[0] ^ X[i]) & P;
+        X[0] ^= t;
+        X[i] ^= t;
+      }
+    }
+  }
+  X[1] ^= X[0];                                     // Gray encode
+  X[2] ^= X[1];
+  uint64_t t = 0;
+  for (uint64_t Q = M; Q > 1; Q >>= 1)
+    if (X[2] & Q) t ^= Q - 1;
+  for (int i = 0; i < 3; ++i) X[i] ^= t;
+  return (spread3(X[0]) << 2) | (spread3(X[1]) << 1) | spread3(X[2]);
+}
+
 // ---------------------------------------------------------------------------
-// system: Morton order and pseudo-atoms
+// system: Hilbert order and pseudo-atoms
 // ---------------------------------------------------------------------------
 void build_system(lsdm_system* s) {
   const i32 n = s->n_atoms;
@@ -98,7 +127,7 @@ void build_system(lsdm_system* s) {
   for (i32 a = 0; a < n; ++a) {
     uint64_t q[3];
     for (int k = 0; k < 3; ++k) q[k] = (uint64_t)std::min(scale, std::max(0.0, std::floor(f[3 * a + k] * scale)));
-    code[a] = spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2);
+    code[a] = hilbert3(q[0], q[1], q[2], 21);
   }
   s->order.resize(n);
   std::iota(s->order.begin(), s->order.end(), 0);
