@@ -102,7 +102,10 @@ def cpu_baseline(cfg, flops_per_atom):
             "seconds": round(dt, 3), "energy_per_atom": r["E"] / s.n, "cpu_model": model}
 
 
-KERNEL_SRC = os.path.join(ROOT, "paper_0911_3584_amd", "csrc", "kernels.hip")
+# sources that decide what the product kernels read and write: the kernels and
+# the symbolic pass (atom order, tiles, steps)
+KERNEL_SRC = [os.path.join(ROOT, "paper_0911_3584_amd", "csrc", f)
+              for f in ("kernels.hip", "symbolic.cpp", "plan_common.h", "lsdm_internal.h")]
 PRODUCT_KERNEL = {"fp64": "k_gprod<double>", "fp32": "k_gprod_rs<float>", "bf16": "k_gprod_bf16",
                   "fp32_rc": "k_gprod_rs<float> (R_A R_B; FP64 corrections in k_rc_apply not counted)"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_si32768.json")
@@ -115,8 +118,11 @@ def workloads_default_name():
 
 def kernel_hash():
     import hashlib
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_per_step(prec, workload):
