@@ -32,9 +32,12 @@
  *     workspace is allocated by the library (hipMalloc) when a handle is
  *     created and released when it is destroyed.
  *   Streams: compute calls enqueue work on `stream` (a hipStream_t, NULL = the
- *     default stream) and return without waiting.  Only *_create calls
- *     synchronise (they read sizes back).  Calls on one handle must not run
- *     concurrently on different streams.
+ *     default stream).  The LNV energy, gradient, shift and electron calls
+ *     return without waiting; *_create calls, the stand-alone multiplies (which
+ *     release their workspaces), the line search and the minimiser (which read
+ *     scalars back) synchronise, and so does the first call that builds a lazy
+ *     map of a handle (transposes, residual-mode maps, the S-in-H map).  Calls
+ *     on one handle must not run concurrently, on one stream or several.
  *   Errors: every call returns LSDM_OK (0) or a negative status; no exception
  *     crosses the ABI; lsdm_last_error() returns a message for the calling
  *     thread's last failure.  A failed call leaves its outputs undefined and
