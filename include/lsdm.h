@@ -224,6 +224,15 @@ int lsdm_lnv_shift(lsdm_lnv* lnv, double alpha, const double* dS, double beta, c
  * LSDM_EDEVICE. */
 int lsdm_lnv_electrons(lsdm_lnv* lnv, int prec, const double* dL, const double* dS, double* dN, double* dGradN,
                        void* stream);
+/* One McWeeny purification step (section 2: eq. 3 read as a map of L, whose
+ * fixed points are idempotent LS): dLout = P_L(3 LSL - 2 LSLSL), both on L's
+ * pattern (device), with every intermediate on the range it needs for an
+ * exact result on L's range (LSL on 2 rL + rS).  The first call builds that
+ * pattern and two plans (synchronous).  Track the electron number of the
+ * iterates with lsdm_lnv_electrons.  prec: LSDM_FP64 or LSDM_FP32.
+ * dLout must not alias dL.  Errors: LSDM_EINVAL, LSDM_EUNSUPPORTED (BF16 or
+ * FP32_RC), LSDM_ENOMEM, LSDM_EDEVICE. */
+int lsdm_lnv_purify(lsdm_lnv* lnv, int prec, const double* dL, const double* dS, double* dLout, void* stream);
 /* Kernel timing of the chain's products: with enable = 1 every product launch
  * of lsdm_lnv_energy(_grad) is bracketed by HIP events recorded on the call's
  * stream (no extra synchronisation); enable = 0 stops and discards. */

@@ -15,8 +15,9 @@ What it computes (Bowler & Miyazaki, section 2 "Methodology"):
   range pattern (matrix multiplication, item 1 of the list of operations);
 * the LNV (McWeeny) density matrix of eq. 3, K = 3 LSL - 2 LSLSL, on H's range;
 * the energy E = 2 Tr(KH) with the spin factor of the electron count
-  N_e = 2 Tr(KS) (constraint 2 of the ground-state search), N_e itself, and the
-  shifted Hamiltonian H - mu S of a chemical potential;
+  N_e = 2 Tr(KS) (constraint 2 of the ground-state search), N_e itself, the
+  shifted Hamiltonian H - mu S of a chemical potential, and one McWeeny step
+  L -> 3 LSL - 2 LSLSL on L's range;
 * dE/dL on L's range, by the analytic formula
   6 (HLS + SLH) - 4 (HLSLS + SLHLS + SLSLH) evaluated through an evaluation
   order different from the forward chain;
@@ -394,6 +395,18 @@ def electron_number(L: Matrix, S: Matrix, rS, rH, rL) -> float:
     pH = pattern(L.pattern.system, rH)
     K = lnv_energy(L, S, zeros(pH), rS, rH, rL)["K"]
     return 2.0 * dot(K.val, project(S, pH).val)
+
+
+def mcweeny(L: Matrix, S: Matrix, rS, rL) -> Matrix:
+    """One McWeeny step on L's range (eq. 3 as a map of L, section 2):
+    P_L(3 LSL - 2 LSLSL), with X = LS on rL + rS and LSL on 2 rL + rS, the
+    ranges an exact result on L's range needs."""
+    sysm = L.pattern.system
+    pL = pattern(sysm, rL)
+    X = multiply(L, S, pattern(sysm, rL + rS))                   # X = LS
+    M = multiply(X, L, pattern(sysm, 2 * rL + rS))               # LSL
+    P = multiply(X, M, pL)                                       # LSLSL on L's range
+    return Matrix(pL, 3.0 * project(M, pL).val - 2.0 * P.val)
 
 
 def lnv_line_coeffs(L: Matrix, D: Matrix, S: Matrix, H: Matrix, rS, rH, rL) -> np.ndarray:

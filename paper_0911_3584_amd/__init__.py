@@ -248,6 +248,16 @@ class LNV:
                                        _dev(G, p["L"].n_values, "G") if grad else None, _stream(stream)))
         return (N, G) if grad else N
 
+    def purify(self, L, S, prec="fp64", out=None, stream=None):
+        """One McWeeny step: 3 LSL - 2 LSLSL on L's pattern (a new tensor unless
+        `out` is given)."""
+        import torch
+        p = self.patterns
+        out = torch.empty(p["L"].n_values, dtype=torch.float64, device=L.device) if out is None else out
+        check(lib().lsdm_lnv_purify(self._h, _prec(prec), _dev(L, p["L"].n_values, "L"), _dev(S, p["S"].n_values, "S"),
+                                    _dev(out, p["L"].n_values, "out"), _stream(stream)))
+        return out
+
     PRODUCTS = ("F1", "F2", "F3", "B1", "B2", "B3", "B4", "B5")
 
     def profile(self, enable=True):

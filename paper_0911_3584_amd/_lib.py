@@ -38,6 +38,7 @@ SIGNATURES = {
     "lsdm_lnv_minimise": (_I, [_P, _I, _P, _P, _P, _I, _D, _D, _P, _P, _P, _P]),
     "lsdm_lnv_shift": (_I, [_P, _D, _P, _D, _P, _P, _P]),
     "lsdm_lnv_electrons": (_I, [_P, _I, _P, _P, _P, _P, _P]),
+    "lsdm_lnv_purify": (_I, [_P, _I, _P, _P, _P, _P]),
     "lsdm_lnv_profile": (_I, [_P, _I]),
     "lsdm_lnv_profile_read": (_I, [_P, _P, _P, _P]),
     "lsdm_lnv_destroy": (None, [_P]),

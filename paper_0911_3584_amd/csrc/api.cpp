@@ -214,6 +214,23 @@ static void multiply_rc(const lsdm_plan* pl, double alpha, const double* dA, con
 // ---------------------------------------------------------------------------
 // the LNV chain
 // ---------------------------------------------------------------------------
+// for every strip of `from`, the strip of `to` with the same (row, column
+// quad, image); `to` must contain `from`
+static std::vector<i64> strip_map(const lsdm_system* sys, const lsdm_pattern* from, const lsdm_pattern* to,
+                                  const char* what) {
+  std::vector<i64> map(from->n_strips, -1);
+  for (i32 q = 0; q < sys->n_pseudo; ++q) {
+    i64 m = to->sptr[q];
+    for (i64 h = from->sptr[q]; h < from->sptr[q + 1]; ++h) {
+      const i64 key = skey(from->squad[h], from->simg[h]);
+      while (m < to->sptr[q + 1] && skey(to->squad[m], to->simg[m]) < key) ++m;
+      if (m >= to->sptr[q + 1] || skey(to->squad[m], to->simg[m]) != key) LSDM_THROW(LSDM_EPATTERN, what);
+      map[h] = m;
+    }
+  }
+  return map;
+}
+
 static void lnv_build(lsdm_lnv* L) {
   const double rS = L->rS, rH = L->rH, rL = L->rL;
   const double rX = rL + rS, rM = std::min(2 * rL + rS, rH + rL + rS);
@@ -235,19 +252,7 @@ static void lnv_build(lsdm_lnv* L) {
   L->B5 = make_plan(L->pX, 0, L->pS, 0, L->pL, h);
   // H strip -> M strip with the same (row, column quad, image); M's range
   // contains H's, so every H strip has one
-  const lsdm_pattern* H = L->pH;
-  const lsdm_pattern* M = L->pM;
-  std::vector<i64> h2m(H->n_strips, -1);
-  for (i32 q = 0; q < L->sys->n_pseudo; ++q) {
-    i64 m = M->sptr[q];
-    for (i64 h = H->sptr[q]; h < H->sptr[q + 1]; ++h) {
-      const i64 key = skey(H->squad[h], H->simg[h]);
-      while (m < M->sptr[q + 1] && skey(M->squad[m], M->simg[m]) < key) ++m;
-      if (m >= M->sptr[q + 1] || skey(M->squad[m], M->simg[m]) != key)
-        LSDM_THROW(LSDM_EPATTERN, "H range exceeds the LSL range");
-      h2m[h] = m;
-    }
-  }
+  const std::vector<i64> h2m = strip_map(L->sys, L->pH, L->pM, "H range exceeds the LSL range");
   L->d_h2m.upload(h2m.data(), sizeof(i64) * h2m.size());
   auto ws = [](DevBuf& b, const lsdm_pattern* p) { b.alloc(strip_bytes(p, sizeof(double))); };
   ws(L->wL, L->pL);
@@ -502,6 +507,58 @@ static void lnv_backward_rc(lsdm_lnv* L, double* dG, hipStream_t st) {
   rc_step(L, 7, wXb, r(RXb), wS, r(RS), wLb, 1.0, 1.0, st);    // Lbar += Xbar S
   if (L->sym) sym_fill<double>(L->pL, wLb, st);
   strip_to_user<double>(L->pL, wLb, dG, st);
+  check_launch();
+}
+
+// ---------------------------------------------------------------------------
+// McWeeny step (section 2: eq. 3 as a map of L, which drives the eigenvalues
+// of LS towards 0 and 1): L' = 3 LSL - 2 LSLSL on L's range.  LSLSL on L's
+// range needs LSL on rL + rX = 2 rL + rS, more than the chain's M when
+// rH < rL; that pattern and its plans are built on the first call.
+// ---------------------------------------------------------------------------
+static void purify_build(lsdm_lnv* L) {
+  std::lock_guard<std::mutex> g(L->pur_mutex);
+  if (L->pur_ready) return;
+  const double rM2 = 2 * L->rL + L->rS;
+  const double rM = std::min(2 * L->rL + L->rS, L->rH + L->rL + L->rS);
+  const lsdm_pattern* M2 = L->pM;
+  if (rM2 > rM) {
+    L->pM2 = make_pattern(L->sys, rM2);
+    L->P2 = make_plan(L->pX, 0, L->pL, 0, L->pM2);
+    M2 = L->pM2;
+    L->wM2.alloc(strip_bytes(M2, sizeof(double)));
+  }
+  L->P3 = make_plan(L->pX, 0, M2, 0, L->pL, L->sym);
+  const std::vector<i64> l2m = strip_map(L->sys, L->pL, M2, "L range exceeds the LSL range");
+  L->d_l2m.upload(l2m.data(), sizeof(i64) * l2m.size());
+  L->wP2.alloc(strip_bytes(L->pL, sizeof(double)));
+  L->wK2.alloc(strip_bytes(L->pL, sizeof(double)));
+  L->pur_ready = true;
+}
+
+template <class T>
+static void purify_chain(lsdm_lnv* L, const double* dL, const double* dS, double* dOut, hipStream_t st) {
+  T* wL = L->wL.as<T>();
+  T* wS = L->wS.as<T>();
+  T* wX = L->wX.as<T>();
+  const lsdm_pattern* M2 = L->pM2 ? L->pM2 : L->pM;
+  T* wM2 = L->pM2 ? L->wM2.as<T>() : L->wM.as<T>();
+  T* wP2 = L->wP2.as<T>();
+  fill<T>(wL, L->pL->n_strips * 64, (T)0, st);
+  fill<T>(wS, L->pS->n_strips * 64, (T)0, st);
+  user_to_strip<T>(L->pL, dL, wL, 1.0, st);
+  user_to_strip<T>(L->pS, dS, wS, 1.0, st);
+  product<T>(L->F1, wL, wS, wX, 1.0, 0.0, st);                       // X = LS
+  if (L->pM2) {
+    product<T>(L->P2, wX, wL, wM2, 1.0, 0.0, st);                    // LSL on 2 rL + rS
+  } else {
+    product<T>(L->F2, wX, wL, wM2, 1.0, 0.0, st);                    // the chain's M suffices
+    if (L->sym) sym_fill<T>(M2, wM2, st);
+  }
+  product<T>(L->P3, wX, wM2, wP2, 1.0, 0.0, st);                     // LSLSL on L's range
+  if (L->sym) sym_fill<T>(L->pL, wP2, st);
+  kassembly_on<T>(L->pL, L->d_l2m.as<i64>(), wM2, wP2, L->wK2.as<double>(), st);   // 3 LSL - 2 LSLSL
+  strip_to_user<double>(L->pL, L->wK2.as<double>(), dOut, st);
   check_launch();
 }
 
@@ -943,6 +1000,20 @@ int lsdm_lnv_electrons(lsdm_lnv* L, int prec, const double* dL, const double* dS
   });
 }
 
+int lsdm_lnv_purify(lsdm_lnv* L, int prec, const double* dL, const double* dS, double* dLout, void* stream) {
+  return guarded([&] {
+    require_device();
+    if (!L || !dL || !dS || !dLout) LSDM_THROW(LSDM_EINVAL, "null argument");
+    if (dLout == dL) LSDM_THROW(LSDM_EINVAL, "dLout must not alias dL");
+    purify_build(L);
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == LSDM_FP64) purify_chain<double>(L, dL, dS, dLout, st);
+    else if (prec == LSDM_FP32) purify_chain<float>(L, dL, dS, dLout, st);
+    else if (prec == LSDM_BF16 || prec == LSDM_FP32_RC) LSDM_THROW(LSDM_EUNSUPPORTED, "purification runs in FP64 or FP32");
+    else LSDM_THROW(LSDM_EINVAL, "unknown precision mode");
+  });
+}
+
 int lsdm_lnv_energy(lsdm_lnv* L, int prec, const double* dL, const double* dS, const double* dH, double* dK,
                     double* dE, void* stream) {
   return guarded([&] {
@@ -1012,8 +1083,8 @@ int lsdm_lnv_profile_read(lsdm_lnv* L, double* ms, int64_t* launches, double* fl
 
 void lsdm_lnv_destroy(lsdm_lnv* L) {
   if (!L) return;
-  for (lsdm_plan* p : {L->F1, L->F2, L->F3, L->B1, L->B2, L->B3, L->B4, L->B5}) delete p;
-  for (lsdm_pattern* p : {L->pS, L->pH, L->pL, L->pX, L->pM}) delete p;
+  for (lsdm_plan* p : {L->F1, L->F2, L->F3, L->B1, L->B2, L->B3, L->B4, L->B5, L->P2, L->P3}) delete p;
+  for (lsdm_pattern* p : {L->pS, L->pH, L->pL, L->pX, L->pM, L->pM2}) delete p;
   delete L;
 }
 

@@ -35,6 +35,9 @@ void to_bf16(const float* in, unsigned short* outR, unsigned short* outC, i64 n,
 void product_bf16(const lsdm_plan* pl, const unsigned short* A, const unsigned short* B, float* C, double alpha,
                   double beta, hipStream_t st);
 template <class T> void kassembly(const lsdm_lnv* L, const T* M, const T* P, double* K, hipStream_t st);
+// K = 3 M|_out - 2 P on an output pattern: map[s] = M's strip with out's strip s key
+template <class T>
+void kassembly_on(const lsdm_pattern* out, const i64* map, const T* M, const T* P, double* K, hipStream_t st);
 template <class T> void scatter_h(const lsdm_lnv* L, const T* H, T* Mb, double scale, hipStream_t st);
 // out[0] = scale * sum a[i] b[i]; partial holds 2 * DOT_BLOCKS doubles
 void dot(const double* a, const double* b, i64 n, double scale, double* partial, double* out, hipStream_t st);

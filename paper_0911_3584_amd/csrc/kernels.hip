@@ -1271,11 +1271,18 @@ void product_bf16(const lsdm_plan* pl, const unsigned short* A, const unsigned s
 }
 
 template <class T>
+void kassembly_on(const lsdm_pattern* out, const i64* map, const T* M, const T* P, double* K, hipStream_t st) {
+  const i64 n = out->n_strips;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_kassembly<T>, dim3(grid_for(n * 64)), dim3(256), 0, st, M, P, K, map,
+                     out->d_smask.as<uint8_t>(), n);
+}
+template void kassembly_on<double>(const lsdm_pattern*, const i64*, const double*, const double*, double*, hipStream_t);
+template void kassembly_on<float>(const lsdm_pattern*, const i64*, const float*, const float*, double*, hipStream_t);
+
+template <class T>
 void kassembly(const lsdm_lnv* L, const T* M, const T* P, double* K, hipStream_t st) {
-  const i64 nh = L->pH->n_strips;
-  if (nh == 0) return;
-  hipLaunchKernelGGL(k_kassembly<T>, dim3(grid_for(nh * 64)), dim3(256), 0, st, M, P, K, L->d_h2m.as<i64>(),
-                     L->pH->d_smask.as<uint8_t>(), nh);
+  kassembly_on<T>(L->pH, L->d_h2m.as<i64>(), M, P, K, st);
 }
 template void kassembly<double>(const lsdm_lnv*, const double*, const double*, double*, hipStream_t);
 template void kassembly<float>(const lsdm_lnv*, const float*, const float*, double*, hipStream_t);

@@ -230,6 +230,14 @@ struct lsdm_lnv {
   bool s2h_ready = false;
   std::mutex s2h_mutex;
   lsdm::DevBuf wSh;                 // S on H's pattern (electron count)
+  // McWeeny step on L's range (built on first use): LSL on 2 rL + rS (pM2,
+  // or M itself when its range is that large), LSLSL on L's range, and the
+  // map from L's strips to pM2's strips
+  lsdm_pattern* pM2 = nullptr;      // owned only when distinct from pM
+  lsdm_plan *P2 = nullptr, *P3 = nullptr;   // P2 null when F2 serves
+  lsdm::DevBuf d_l2m, wM2, wP2, wK2;
+  bool pur_ready = false;
+  std::mutex pur_mutex;
   // optional kernel timing: event pairs around product launches
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;

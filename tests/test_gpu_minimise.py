@@ -140,3 +140,47 @@ def test_minimise_symmetric_mode_matches():
     E2, g2 = sym.minimise(T(v["L"]).clone(), T(v["S"]), sym.shift(T(v["S"]), T(v["H"]), mu=1.0), max_iter=6, gtol=0.0)
     np.testing.assert_allclose(E2, E1, rtol=1e-10)
     np.testing.assert_allclose(g2, g1, rtol=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# McWeeny purification step
+# ---------------------------------------------------------------------------
+PURIFY_CASES = {
+    "si64_rl12": lambda: (workloads.workload("si64_rl12")["system"], 8.0, 12.0, 12.0),     # the chain's LSL serves
+    "si64_jitter_rl16": lambda: (workloads.diamond(2, jitter=0.1, seed=7), 8.0, 12.0, 16.0),  # own LSL pattern (rH < rL)
+    "mixed_box_13_5": lambda: (workloads.random_box(300, 17.5, 240, 13, 5, seed=2), 6.0, 8.0, 8.0),
+    "si_slab_h_2x2x2": lambda: (workloads.si_slab((2, 2, 2)), 8.0, 12.0, 16.0),
+}
+
+
+@pytest.mark.parametrize("symmetric", [False, True], ids=["full", "sym"])
+@pytest.mark.parametrize("name", list(PURIFY_CASES))
+def test_purify_parity(name, symmetric):
+    s, rS, rH, rL = PURIFY_CASES[name]()
+    say(f"[purify] {name} atoms={s.n} symmetric={symmetric}")
+    lnv = lsdm.LNV(lsdm.System.from_workload(s), rS, rH, rL, symmetric=symmetric)
+    v = {w: gpu_values(lnv.patterns[w], s, w, rS=rS) for w in "LS"}
+    inp = oracle.make_inputs(s, rS, rH, rL)
+    ref = oracle.mcweeny(inp["L"], inp["S"], rS, rL)
+    out = lnv.purify(T(v["L"]), T(v["S"])).cpu().numpy()
+    assert rel(out, ref.val) <= 1e-12, rel(out, ref.val)
+    out32 = lnv.purify(T(v["L"]), T(v["S"]), prec="fp32").cpu().numpy()
+    assert rel(out32, ref.val) <= 1e-5, rel(out32, ref.val)
+
+
+def test_purify_iterates_and_electron_count():
+    """Three McWeeny steps on the 64-atom cell against the oracle's, with the
+    electron number of each iterate."""
+    s, (rS, rH, rL), lnv, v, inp = _si64()
+    L = T(v["L"])
+    Lr = inp["L"]
+    for it in range(3):
+        L = lnv.purify(L, T(v["S"]))
+        Lr = oracle.mcweeny(Lr, inp["S"], rS, rL)
+        assert rel(L.cpu().numpy(), Lr.val) <= 1e-11, it
+        N = lnv.electrons(L, T(v["S"])).item()
+        Nr = oracle.electron_number(Lr, inp["S"], rS, rH, rL)
+        assert abs(N - Nr) <= 1e-11 * abs(Nr), (it, N, Nr)
+        say(f"    step {it}: N_e = {N:.10f}")
+    with pytest.raises(lsdm.LsdmError):
+        lnv.purify(L, T(v["S"]), prec="bf16")

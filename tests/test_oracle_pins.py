@@ -605,3 +605,48 @@ def test_minimiser_grand_potential_closed_form():
     Lf, Es, gs = oracle.lnv_minimise(L0, S, Hm, rS, rH, rL, max_iter=80, gtol=1e-11)
     assert abs(Es[-1] - (-5.4 * s.n)) <= 1e-12 * 5.4 * s.n
     assert abs(oracle.electron_number(Lf, S, rS, rH, rL) - 6.0 * s.n) <= 1e-9 * s.n
+
+
+# ---------------------------------------------------------------------------
+# McWeeny purification step (eq. 3 as a map of L)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mixed", [False, True])
+def test_mcweeny_vs_dense(mixed):
+    """One step equals the untruncated 3LSL - 2LSLSL restricted to L's pattern."""
+    s = _cluster(n=36, edge=13.0, mixed=mixed, seed=12)
+    rS, rH, rL = 4.0, 5.0, 5.5
+    inp = _inputs(s, rS, rH, rL)
+    L, S = _dense.to_dense(inp["L"]), _dense.to_dense(inp["S"])
+    ref = (3 * L @ S @ L - 2 * L @ S @ L @ S @ L) * _dense.mask_dense(inp["L"].pattern)
+    got = _dense.to_dense(oracle.mcweeny(inp["L"], inp["S"], rS, rL))
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+
+
+def test_mcweeny_closed_forms():
+    """On-site blocks, S = I: L = l I maps to (3 l^2 - 2 l^3) I, and a projector
+    is a fixed point."""
+    s, (rS, rH, rL), _, S, H, P, _ = onsite_minimiser_case()
+    pL = oracle.pattern(s, rL)
+    for l in (0.2, 0.5, 0.9, 1.2):
+        L = oracle.Matrix(pL, np.tile(l * np.eye(4).ravel(), s.n))
+        out = oracle.mcweeny(L, S, rS, rL)
+        np.testing.assert_allclose(out.val, np.tile((3 * l * l - 2 * l ** 3) * np.eye(4).ravel(), s.n), atol=1e-15)
+    Lp = oracle.Matrix(pL, P)
+    np.testing.assert_allclose(oracle.mcweeny(Lp, S, rS, rL).val, P, atol=1e-14)
+
+
+def test_mcweeny_iteration_reaches_projector():
+    """With every pair in range, iterating the step maps each eigenvalue of LS
+    in (-1/2, 3/2) through 3x^2 - 2x^3 towards 0 (below 1/2) or 1 (above): LS
+    becomes idempotent and Tr(LS) counts the eigenvalues above 1/2."""
+    s, R = _full_range_cluster(n=10, seed=8)
+    inp = _inputs(s, R, R, R)
+    S = _dense.to_dense(inp["S"])
+    lam = np.linalg.eigvals(_dense.to_dense(inp["L"]) @ S).real
+    assert lam.min() > -0.5 and lam.max() < 1.5 and np.all(np.abs(lam - 0.5) > 1e-3)
+    L = inp["L"]
+    for _ in range(40):
+        L = oracle.mcweeny(L, inp["S"], R, R)
+    LS = _dense.to_dense(L) @ S
+    np.testing.assert_allclose(LS @ LS, LS, atol=1e-9)
+    assert abs(np.trace(LS) - np.sum(lam > 0.5)) < 1e-9
