@@ -334,9 +334,8 @@ static void lnv_backward(lsdm_lnv* L, double* dG, hipStream_t st) {
   T* wMb = L->wMb.as<T>();
   T* wXb = L->wXb.as<T>();
   T* wLb = L->wLb.as<T>();
-  fill<T>(wMb, L->pM->n_strips * 64, (T)0, st);
-  scatter_h<T>(L, wH, wMb, 6.0, st);                // Mbar = 3 Kbar = 6H on H's range
-  chain_product<T>(L, 3, wX, wH, wMb, -4.0, 1.0, st);    // Mbar += X^T Pbar,  Pbar = -4H
+  chain_product<T>(L, 3, wX, wH, wMb, -4.0, 0.0, st);    // Mbar = X^T Pbar,  Pbar = -4H (every M strip written)
+  scatter_h<T>(L, wH, wMb, 6.0, st);                // Mbar += 3 Kbar = 6H on H's range
   chain_product<T>(L, 4, wH, wM, wXb, -4.0, 0.0, st);    // Xbar  = Pbar M
   chain_product<T>(L, 5, wMb, wL, wXb, 1.0, 1.0, st);    // Xbar += Mbar L
   chain_product<T>(L, 6, wX, wMb, wLb, 1.0, 0.0, st);    // Lbar  = X^T Mbar
@@ -419,9 +418,8 @@ static void lnv_backward_bf16(lsdm_lnv* L, double* dG, hipStream_t st) {
   float* wMb = L->wMb.as<float>();
   float* wXb = L->wXb.as<float>();
   float* wLb = L->wLb.as<float>();
-  fill<float>(wMb, L->pM->n_strips * 64, 0.f, st);
-  scatter_h<float>(L, wH, wMb, 6.0, st);
-  chain_product_bf16(L, 3, h(XC), h(HC), wMb, -4.0, 1.0, st);   // Mbar += X^T Pbar
+  chain_product_bf16(L, 3, h(XC), h(HC), wMb, -4.0, 0.0, st);   // Mbar = X^T Pbar
+  scatter_h<float>(L, wH, wMb, 6.0, st);                          // Mbar += 6H
   to_bf16(wMb, h(MbR), h(MbC), L->pM->n_strips * 64, st);
   chain_product_bf16(L, 4, h(HR), h(MC), wXb, -4.0, 0.0, st);   // Xbar = Pbar M
   chain_product_bf16(L, 5, h(MbR), h(LC), wXb, 1.0, 1.0, st);   // Xbar += Mbar L
@@ -496,9 +494,8 @@ static void lnv_backward_rc(lsdm_lnv* L, double* dG, hipStream_t st) {
   double* wMb = L->wMb.as<double>();
   double* wXb = L->wXb.as<double>();
   double* wLb = L->wLb.as<double>();
-  fill<double>(wMb, L->pM->n_strips * 64, 0.0, st);
-  scatter_h<double>(L, wH, wMb, 6.0, st);
-  rc_step(L, 3, wX, r(RX), wH, r(RH), wMb, -4.0, 1.0, st);     // Mbar += X^T Pbar
+  rc_step(L, 3, wX, r(RX), wH, r(RH), wMb, -4.0, 0.0, st);     // Mbar = X^T Pbar
+  scatter_h<double>(L, wH, wMb, 6.0, st);                      // Mbar += 6H
   offsite_f32(L->pM, wMb, r(RMb), st);
   rc_step(L, 4, wH, r(RH), wM, r(RM), wXb, -4.0, 0.0, st);     // Xbar = Pbar M
   rc_step(L, 5, wMb, r(RMb), wL, r(RL), wXb, 1.0, 1.0, st);    // Xbar += Mbar L

@@ -992,13 +992,13 @@ __global__ void k_kassembly(const T* __restrict__ M, const T* __restrict__ P, do
   }
 }
 
-// Mbar = scale * H scattered into M's strips (the rest of Mbar is cleared first)
+// Mbar += scale * H on H's blocks (H's strips mapped into M's strips)
 template <class T>
 __global__ void k_scatter_h(const T* __restrict__ H, T* __restrict__ Mb, const i64* __restrict__ h2m, i64 nh, T scale) {
   for (i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x; g < nh * 64; g += (i64)gridDim.x * blockDim.x) {
     const i64 h = g >> 6;
     const int e = (int)(g & 63);
-    Mb[h2m[h] * 64 + e] = scale * H[g];
+    Mb[h2m[h] * 64 + e] += scale * H[g];
   }
 }
 
