@@ -109,8 +109,10 @@ void lsdm_pattern_destroy(lsdm_pattern* p);
  * (i,k,j) grouped into tiles (16 output rows x 32 output columns of pseudo-
  * atoms) and steps (one inner pseudo-atom k of a tile) for the GPU kernels:
  * the tiles and their inner lists are built on the host (multithreaded), the
- * steps are generated and kept on the device.  Without a device only the
- * counts are computed (plan_info works, products fail with LSDM_EDEVICE).
+ * steps are generated and kept on the device.  The plan also holds the
+ * per-XCD tile counters its product launches use, so one plan serves one
+ * product at a time.  Without a device only the counts are computed
+ * (plan_info works, products fail with LSDM_EDEVICE).
  * Errors: LSDM_EPATTERN (patterns of different systems), LSDM_ENOMEM. */
 int lsdm_plan_create(const lsdm_pattern* A, int transA, const lsdm_pattern* B, int transB,
                      const lsdm_pattern* C, lsdm_plan** out);

@@ -416,7 +416,7 @@ __global__ void __launch_bounds__(256) k_gprod(const GTile* __restrict__ tiles, 
                                                const GStep* __restrict__ steps, const T* __restrict__ A,
                                                const T* __restrict__ B, T* __restrict__ C,
                                                const uint8_t* __restrict__ cmask, T alpha, T beta, int na_blk,
-                                               int nb_str) {
+                                               int nb_str, unsigned long long* __restrict__ queue) {
   typedef typename Mma16<T>::acc_t acc_t;
   typedef GLayout<T> L;
   constexpr bool F64 = sizeof(T) == 8;
@@ -436,12 +436,17 @@ __global__ void __launch_bounds__(256) k_gprod(const GTile* __restrict__ tiles, 
   const int b_off = ((lane & 15) >> 2) * 16 + kk * 4 + (lane & 3);
   const int abit = 4 * wave + ai;
   // contiguous tile ranges per XCD (workgroups are dealt to the 8 XCDs round
-  // robin), so concurrent tiles of one XCD share A and B through its L2
-  const i64 xcd = blockIdx.x & 7, nbx = gridDim.x >> 3, lb = blockIdx.x >> 3;
+  // robin), taken in order from the XCD's counter queue[xcd] (zero at launch)
+  const i64 xcd = blockIdx.x & 7;
   const i64 t_begin = ntiles * xcd / 8, t_end = ntiles * (xcd + 1) / 8;
   const char* recs = reinterpret_cast<const char*>(steps);
+  __shared__ i64 t_next;
 
-  for (i64 t = t_begin + lb; t < t_end; t += nbx) {
+  for (;;) {
+    if (threadIdx.x == 0) t_next = t_begin + (i64)atomicAdd(&queue[xcd], 1ull);
+    __syncthreads();
+    const i64 t = t_next;
+    if (t >= t_end) break;
     const GTile* tp = tiles + uniform64(t);
     const i64 s0 = tp->step0;
     const int ns = tp->nsteps;
@@ -521,7 +526,7 @@ __global__ void __launch_bounds__(256) k_gprod_rs(const GTile* __restrict__ tile
                                                const GStep* __restrict__ steps, const T* __restrict__ A,
                                                const T* __restrict__ B, T* __restrict__ C,
                                                const uint8_t* __restrict__ cmask, T alpha, T beta, int na_blk,
-                                               int nb_str) {
+                                               int nb_str, unsigned long long* __restrict__ queue) {
   typedef typename Mma16<T>::acc_t acc_t;
   constexpr bool F64 = sizeof(T) == 8;
   constexpr int SB = LSDM_GSB_RS;
@@ -548,12 +553,19 @@ __global__ void __launch_bounds__(256) k_gprod_rs(const GTile* __restrict__ tile
   const int b_off = ((lane & 15) >> 2) * 16 + kk * 4 + (lane & 3);
   const int abit = 4 * wave + ai;
   // contiguous tile ranges per XCD (workgroups are dealt to the 8 XCDs round
-  // robin), so concurrent tiles of one XCD share A and B through its L2
-  const i64 xcd = blockIdx.x & 7, nbx = gridDim.x >> 3, lb = blockIdx.x >> 3;
+  // robin), so concurrent tiles of one XCD share A and B through its L2; the
+  // workgroups of an XCD take its tiles in order from a counter (queue[xcd],
+  // zero at launch), so uneven tiles do not leave a long tail
+  const i64 xcd = blockIdx.x & 7;
   const i64 t_begin = ntiles * xcd / 8, t_end = ntiles * (xcd + 1) / 8;
   const i4v* recs = reinterpret_cast<const i4v*>(steps);
+  __shared__ i64 t_next;
 
-  for (i64 t = t_begin + lb; t < t_end; t += nbx) {
+  for (;;) {
+    if (threadIdx.x == 0) t_next = t_begin + (i64)atomicAdd(&queue[xcd], 1ull);
+    __syncthreads();
+    const i64 t = t_next;
+    if (t >= t_end) break;
     const GTile* tp = tiles + uniform64(t);
     const i64 s0 = tp->step0;
     const int ns = tp->nsteps;
@@ -700,7 +712,8 @@ __global__ void __launch_bounds__(256) k_gprod_bf16(const GTile* __restrict__ ti
                                                     const GStep* __restrict__ steps,
                                                     const unsigned short* __restrict__ A,
                                                     const unsigned short* __restrict__ B, float* __restrict__ C,
-                                                    const uint8_t* __restrict__ cmask, float alpha, float beta) {
+                                                    const uint8_t* __restrict__ cmask, float alpha, float beta,
+                                                    unsigned long long* __restrict__ queue) {
   constexpr int SB = 8;                 // steps per batch: two MFMA groups of KG steps
   constexpr int KG = 4;
   constexpr int AV = GROWS * 16;
@@ -725,11 +738,17 @@ __global__ void __launch_bounds__(256) k_gprod_bf16(const GTile* __restrict__ ti
   const int b_off = ((lane & 15) >> 2) * 16 + (lane & 3) * 4;
   const int abit = 4 * wave + ai;
   constexpr uint32_t COL = 1u | (1u << GJ) | (1u << (2 * GJ)) | (1u << (3 * GJ));
-  const i64 xcd = blockIdx.x & 7, nbx = gridDim.x >> 3, lb = blockIdx.x >> 3;
+  // tiles of the XCD taken in order from its counter queue[xcd] (zero at launch)
+  const i64 xcd = blockIdx.x & 7;
   const i64 t_begin = ntiles * xcd / 8, t_end = ntiles * (xcd + 1) / 8;
   const i4v* recs = reinterpret_cast<const i4v*>(steps);
+  __shared__ i64 t_next;
 
-  for (i64 t = t_begin + lb; t < t_end; t += nbx) {
+  for (;;) {
+    if (threadIdx.x == 0) t_next = t_begin + (i64)atomicAdd(&queue[xcd], 1ull);
+    __syncthreads();
+    const i64 t = t_next;
+    if (t >= t_end) break;
     const GTile* tp = tiles + uniform64(t);
     const i64 s0 = tp->step0;
     const int ns = tp->nsteps;
@@ -1146,6 +1165,10 @@ static unsigned gproduct_grid(K kernel, i64 ntiles) {
   return (unsigned)blocks;
 }
 
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+}
+
 template <class T>
 void product(const lsdm_plan* pl, const T* A, const T* B, T* C, double alpha, double beta, hipStream_t st) {
   if (pl->n_gtiles == 0) return;
@@ -1156,19 +1179,23 @@ void product(const lsdm_plan* pl, const T* A, const T* B, T* C, double alpha, do
   // operand array bounds for the index clamp (a plan with steps has both)
   const int na = (int)std::max<i64>(1, pl->A->n_strips * 4), nbs = (int)std::max<i64>(1, pl->B->n_strips);
   if constexpr (sizeof(T) == 4) {
+    unsigned long long* q = pl->d_queue.as<unsigned long long>();
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, q, 8);
     if (pl->transA)
       hipLaunchKernelGGL((k_gprod_rs<T, true>), dim3(gproduct_grid(k_gprod_rs<T, true>, pl->n_gtiles)), b, 0, st, Tl,
-                         pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta, na, nbs);
+                         pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta, na, nbs, q);
     else
       hipLaunchKernelGGL((k_gprod_rs<T, false>), dim3(gproduct_grid(k_gprod_rs<T, false>, pl->n_gtiles)), b, 0, st,
-                         Tl, pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta, na, nbs);
+                         Tl, pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta, na, nbs, q);
   } else {
+    unsigned long long* q = pl->d_queue.as<unsigned long long>();
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, q, 8);
     if (pl->transA)
       hipLaunchKernelGGL((k_gprod<T, true>), dim3(gproduct_grid(k_gprod<T, true>, pl->n_gtiles)), b, 0, st, Tl,
-                         pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta, na, nbs);
+                         pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta, na, nbs, q);
     else
       hipLaunchKernelGGL((k_gprod<T, false>), dim3(gproduct_grid(k_gprod<T, false>, pl->n_gtiles)), b, 0, st, Tl,
-                         pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta, na, nbs);
+                         pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta, na, nbs, q);
   }
 }
 template void product<double>(const lsdm_plan*, const double*, const double*, double*, double, double, hipStream_t);
@@ -1262,12 +1289,14 @@ void product_bf16(const lsdm_plan* pl, const unsigned short* A, const unsigned s
   const GStep* S = pl->d_gsteps.as<GStep>();
   const uint8_t* cm = pl->C->d_smask.as<uint8_t>();
   const dim3 b(256);
+  unsigned long long* q = pl->d_queue.as<unsigned long long>();
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, q, 8);
   if (pl->transA)
     hipLaunchKernelGGL((k_gprod_bf16<true>), dim3(gproduct_grid(k_gprod_bf16<true>, pl->n_gtiles)), b, 0, st, Tl,
-                       pl->n_gtiles, S, A, B, C, cm, (float)alpha, (float)beta);
+                       pl->n_gtiles, S, A, B, C, cm, (float)alpha, (float)beta, q);
   else
     hipLaunchKernelGGL((k_gprod_bf16<false>), dim3(gproduct_grid(k_gprod_bf16<false>, pl->n_gtiles)), b, 0, st, Tl,
-                       pl->n_gtiles, S, A, B, C, cm, (float)alpha, (float)beta);
+                       pl->n_gtiles, S, A, B, C, cm, (float)alpha, (float)beta, q);
 }
 
 template <class T>

@@ -188,6 +188,7 @@ struct lsdm_plan {
   // group tiles and their steps
   lsdm::i64 n_gtiles = 0, n_gsteps = 0;
   lsdm::DevBuf d_gtiles, d_gsteps;
+  lsdm::DevBuf d_queue;             // per-XCD tile counters of the product kernels (8 x u64)
   // residual mode (built on first use): for every output block, the B blocks
   // (p', q, n) with p' in p's atom and the op(A) blocks (p, q', n) with q' in
   // q's atom (rc_np per block, block index = value offset / 16, -1 if absent);

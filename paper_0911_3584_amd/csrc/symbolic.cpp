@@ -551,6 +551,7 @@ void build_plan(lsdm_plan* pl) {
   }
   const i64 ntile = (i64)allT.size();
   pl->n_gtiles = ntile;
+  pl->d_queue.alloc(8 * sizeof(unsigned long long));
   if (have_device()) {
     DevBuf d_k, d_kb, d_cnt, d_work;
     d_k.upload(allK.data(), sizeof(GKEnt) * allK.size());
