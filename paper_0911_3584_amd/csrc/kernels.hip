@@ -253,6 +253,27 @@ __global__ void __launch_bounds__(256) k_plan_gsteps(const GTile* __restrict__ t
 // Rows without an A block are zeroed when the operand is read from LDS; a
 // column whose B strip is absent has no active slot and issues no MFMA.
 // ---------------------------------------------------------------------------
+// Tile scheduling of the product kernels.  XCD x owns the contiguous tile
+// range [ntiles x / 8, ntiles (x + 1) / 8) (workgroups are dealt to the 8 XCDs
+// round robin, so concurrent tiles of one XCD share operands through its L2)
+// and its workgroups take those tiles in order from the counter queue[x]
+// (zero at launch).  A workgroup whose XCD has run out takes tiles from the
+// other XCDs' counters (XCD x+1, x+2, ...), so the launch ends when all tiles
+// are taken; -1 then.  Called by one thread; `victim` (0 .. 8) is that
+// thread's position in the XCD order and only grows.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ i64 next_tile(unsigned long long* queue, i64 ntiles, int xcd, int& victim) {
+  while (victim < 8) {
+    const int x = (xcd + victim) & 7;
+    const i64 b = ntiles * x / 8, e = ntiles * (x + 1) / 8;
+    const i64 t = b + (i64)atomicAdd(&queue[x], 1ull);
+    if (t < e) return t;
+    ++victim;
+  }
+  return -1;
+}
+
+// ---------------------------------------------------------------------------
 // Steps per staged batch and copy lookahead (LDS per workgroup: (DA+1) SB
 // steps of operands and (DA+2) SB records).
 #ifndef LSDM_GSB_F32
@@ -435,18 +456,17 @@ __global__ void __launch_bounds__(256) k_gprod(const GTile* __restrict__ tiles, 
   const int a_off = (4 * wave + ai) * 16 + (TA ? (kk * 4 + ar) : (ar * 4 + kk));
   const int b_off = ((lane & 15) >> 2) * 16 + kk * 4 + (lane & 3);
   const int abit = 4 * wave + ai;
-  // contiguous tile ranges per XCD (workgroups are dealt to the 8 XCDs round
-  // robin), taken in order from the XCD's counter queue[xcd] (zero at launch)
-  const i64 xcd = blockIdx.x & 7;
-  const i64 t_begin = ntiles * xcd / 8, t_end = ntiles * (xcd + 1) / 8;
+  // tiles: see next_tile
+  const int xcd = (int)(blockIdx.x & 7);
+  int victim = 0;
   const char* recs = reinterpret_cast<const char*>(steps);
   __shared__ i64 t_next;
 
   for (;;) {
-    if (threadIdx.x == 0) t_next = t_begin + (i64)atomicAdd(&queue[xcd], 1ull);
+    if (threadIdx.x == 0) t_next = next_tile(queue, ntiles, xcd, victim);
     __syncthreads();
     const i64 t = t_next;
-    if (t >= t_end) break;
+    if (t < 0) break;
     const GTile* tp = tiles + uniform64(t);
     const i64 s0 = tp->step0;
     const int ns = tp->nsteps;
@@ -552,20 +572,17 @@ __global__ void __launch_bounds__(256) k_gprod_rs(const GTile* __restrict__ tile
   const int a_off = (4 * wave + ai) * 16 + (TA ? (kk * 4 + ar) : (ar * 4 + kk));
   const int b_off = ((lane & 15) >> 2) * 16 + kk * 4 + (lane & 3);
   const int abit = 4 * wave + ai;
-  // contiguous tile ranges per XCD (workgroups are dealt to the 8 XCDs round
-  // robin), so concurrent tiles of one XCD share A and B through its L2; the
-  // workgroups of an XCD take its tiles in order from a counter (queue[xcd],
-  // zero at launch), so uneven tiles do not leave a long tail
-  const i64 xcd = blockIdx.x & 7;
-  const i64 t_begin = ntiles * xcd / 8, t_end = ntiles * (xcd + 1) / 8;
+  // tiles: see next_tile (per-XCD counters, then the other XCDs' tiles)
+  const int xcd = (int)(blockIdx.x & 7);
+  int victim = 0;
   const i4v* recs = reinterpret_cast<const i4v*>(steps);
   __shared__ i64 t_next;
 
   for (;;) {
-    if (threadIdx.x == 0) t_next = t_begin + (i64)atomicAdd(&queue[xcd], 1ull);
+    if (threadIdx.x == 0) t_next = next_tile(queue, ntiles, xcd, victim);
     __syncthreads();
     const i64 t = t_next;
-    if (t >= t_end) break;
+    if (t < 0) break;
     const GTile* tp = tiles + uniform64(t);
     const i64 s0 = tp->step0;
     const int ns = tp->nsteps;
@@ -738,17 +755,17 @@ __global__ void __launch_bounds__(256) k_gprod_bf16(const GTile* __restrict__ ti
   const int b_off = ((lane & 15) >> 2) * 16 + (lane & 3) * 4;
   const int abit = 4 * wave + ai;
   constexpr uint32_t COL = 1u | (1u << GJ) | (1u << (2 * GJ)) | (1u << (3 * GJ));
-  // tiles of the XCD taken in order from its counter queue[xcd] (zero at launch)
-  const i64 xcd = blockIdx.x & 7;
-  const i64 t_begin = ntiles * xcd / 8, t_end = ntiles * (xcd + 1) / 8;
+  // tiles: see next_tile (per-XCD counters, then the other XCDs' tiles)
+  const int xcd = (int)(blockIdx.x & 7);
+  int victim = 0;
   const i4v* recs = reinterpret_cast<const i4v*>(steps);
   __shared__ i64 t_next;
 
   for (;;) {
-    if (threadIdx.x == 0) t_next = t_begin + (i64)atomicAdd(&queue[xcd], 1ull);
+    if (threadIdx.x == 0) t_next = next_tile(queue, ntiles, xcd, victim);
     __syncthreads();
     const i64 t = t_next;
-    if (t >= t_end) break;
+    if (t < 0) break;
     const GTile* tp = tiles + uniform64(t);
     const i64 s0 = tp->step0;
     const int ns = tp->nsteps;
