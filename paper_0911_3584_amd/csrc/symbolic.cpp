@@ -183,8 +183,9 @@ void build_pattern_blocks(lsdm_pattern* p) {
       const double w = 1.0 / bn;   // distance between the lattice planes of axis k
       const double width = std::max(R * (1.0 + 1e-9), 1e-300);
       nb[k] = (int)std::max(1.0, std::min(1024.0, std::floor(w / width)));
-      D[k] = (int)std::floor(R * nb[k] / w) + 1;
-      if (2 * D[k] + 1 > 255) LSDM_THROW(LSDM_EUNSUPPORTED, "range too large for the image encoding");
+      const double Dk = std::floor(R * nb[k] / w) + 1.0;   // checked before the conversion to int
+      if (!(2.0 * Dk + 1.0 <= 255.0)) LSDM_THROW(LSDM_EUNSUPPORTED, "range too large for the image encoding");
+      D[k] = (int)Dk;
     }
     for (i32 a = 0; a < n; ++a)
       for (int k = 0; k < 3; ++k) {

@@ -117,6 +117,11 @@ def test_errors():
     with pytest.raises(lsdm.LsdmError) as e:
         lsdm.System(s.xyz, s.nfn, sing)
     assert e.value.code == lsdm._lib.EINVAL
+    # ranges far beyond what the image encoding can hold fail cleanly, however large
+    for huge in (3000.0, 1e5, 1e12, 1e300):
+        with pytest.raises(lsdm.LsdmError) as e:
+            lsdm.Pattern(gs, huge)
+        assert e.value.code == lsdm._lib.EUNSUPPORTED
     h = ctypes.c_void_p()
     rc = lsdm.lib().lsdm_lnv_create_ex(gs._h, 4.0, 5.0, 5.0, 2, ctypes.byref(h))
     assert rc == lsdm._lib.EINVAL and not h.value
