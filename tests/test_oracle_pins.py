@@ -650,3 +650,25 @@ def test_mcweeny_iteration_reaches_projector():
     LS = _dense.to_dense(L) @ S
     np.testing.assert_allclose(LS @ LS, LS, atol=1e-9)
     assert abs(np.trace(LS) - np.sum(lam > 0.5)) < 1e-9
+
+
+# ---------------------------------------------------------------------------
+# stored oracle results (tests/golden, written by tests/golden/make_golden.py)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["si64_rl12", "mixed_cluster_40"])
+def test_oracle_matches_stored_results(name):
+    import json
+    import os
+    import importlib.util
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("make_golden", os.path.join(here, "make_golden.py"))
+    mg = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mg)
+    ref = json.load(open(os.path.join(here, f"oracle_{name}.json")))
+    case = next(c for c in mg.cases() if c[0] == name)
+    got = mg.record(*case)
+    for key in ("E", "N_e", "grad_norm"):
+        assert abs(got[key] - ref[key]) <= 1e-13 * abs(ref[key]), key
+    for key in ("grad_samples", "K_samples"):
+        for i, v in ref[key].items():
+            assert abs(got[key][i] - v) <= 1e-13 * max(abs(v), 1e-3), (key, i)
