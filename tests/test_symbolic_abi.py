@@ -141,3 +141,13 @@ def test_compute_without_device_fails_loudly():
     p = lsdm.Pattern(gs, 5.0)
     rc = lsdm.lib().lsdm_dot(p._h, ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(8), None)
     assert rc == lsdm._lib.EDEVICE
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 exits with a message."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0 and "one GPU" in r.stderr and r.stdout == ""
