@@ -157,10 +157,12 @@ int lsdm_lnv_create(const lsdm_system* sys, double rS, double rH, double rL, lsd
 enum {
   /* Symmetric inputs (section 2: S and H of a real basis, and L built like K,
    * are symmetric: block (j,i,-n) = block (i,j,n)^T).  M = LSL, P = LSLSL and
-   * dE/dL are then symmetric too, so the products that make them (X L, X M
-   * and the two terms of dE/dL) compute one half of their output strips and
-   * the other half is filled with transposes (28 % fewer flops per
-   * energy-and-gradient step on the 32,768-atom Si cell, ranges 8/12/16).  Every L passed to a handle made with this flag
+   * dE/dL are then symmetric too.  The products X L and X M compute one half
+   * of their output strips and the other half is filled with transposes, and
+   * the adjoint takes dE/dL as V + V^T - 4 X^T H X with X = LS and
+   * V = 6 HX - 4 HMS (the same terms as the gradient of eq. 3, regrouped;
+   * X^T H X on one half).  Together: 48 % fewer flops per energy-and-gradient
+   * step on the 32,768-atom Si cell, ranges 8/12/16.  Every L passed to a handle made with this flag
    * (also L + tD in a line search) must be symmetric; for a non-symmetric L
    * the results are those of the computed half mirrored, not of eq. 3. */
   LSDM_LNV_SYMMETRIC = 1

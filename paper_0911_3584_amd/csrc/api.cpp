@@ -13,6 +13,18 @@
 //             B5  Lbar += P_L(Xbar S)
 // Taking LSLSL as X M = (LS)(LSL) keeps the chain equal to eq. 3 for any L, so
 // the adjoint yields dE/dL of eq. 3 itself: 6 (HLS + SLH) - 4 (HLSLS + SLHLS + SLSLH).
+// Symmetric mode (S, H, L symmetric, so Xᵀ = SL and M = LSL are known
+// transposes) groups the same terms as dE/dL = V + Vᵀ - 4 XᵀHX with
+// V = 6 HX - 4 HMS, each on L's range:
+//             B1  Mbar = P_M(X^T Pbar)            (no 6H)
+//             B2  Xbar = P_X(Pbar M)              (= -4 HM)
+//             B3  Lbar = P_L(Mbar X)              (= -4 XᵀHX, symmetric: half)
+//             B4  V    = P_L(6 H X)
+//             B5  V   += P_L(Xbar S)
+//             Lbar += V + Vᵀ, then the dropped half is mirrored.
+// Every truncation keeps what L's range reaches: X's range holds all of
+// P_X(HM) that (HM)S needs on L, and M's range all of P_M(XᵀH) that (XᵀH)X
+// needs on L, so the regrouped chain equals the one above up to rounding.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -240,16 +252,21 @@ static void lnv_build(lsdm_lnv* L) {
   L->pX = make_pattern(L->sys, rX);
   L->pM = make_pattern(L->sys, rM);
   L->F1 = make_plan(L->pL, 0, L->pS, 0, L->pX);
-  // symmetric mode: M = LSL, P = LSLSL and dE/dL are symmetric, so their
-  // products (F2, F3, and B4 + B5, whose sum is dE/dL) fill one half
+  // symmetric mode: M = LSL, P = LSLSL and XᵀHX are symmetric, so their
+  // products (F2, F3, B3 of the regrouped adjoint) fill one half
   const bool h = L->sym;
   L->F2 = make_plan(L->pX, 0, L->pL, 0, L->pM, h);
   L->F3 = make_plan(L->pX, 0, L->pM, 0, L->pH, h);
   L->B1 = make_plan(L->pX, 1, L->pH, 0, L->pM);
   L->B2 = make_plan(L->pH, 0, L->pM, 0, L->pX);
-  L->B3 = make_plan(L->pM, 0, L->pL, 0, L->pX);
-  L->B4 = make_plan(L->pX, 1, L->pM, 0, L->pL, h);
-  L->B5 = make_plan(L->pX, 0, L->pS, 0, L->pL, h);
+  if (h) {
+    L->B3 = make_plan(L->pM, 0, L->pX, 0, L->pL, true);
+    L->B4 = make_plan(L->pH, 0, L->pX, 0, L->pL);
+  } else {
+    L->B3 = make_plan(L->pM, 0, L->pL, 0, L->pX);
+    L->B4 = make_plan(L->pX, 1, L->pM, 0, L->pL);
+  }
+  L->B5 = make_plan(L->pX, 0, L->pS, 0, L->pL);
   // H strip -> M strip with the same (row, column quad, image); M's range
   // contains H's, so every H strip has one
   const std::vector<i64> h2m = strip_map(L->sys, L->pH, L->pM, "H range exceeds the LSL range");
@@ -266,6 +283,7 @@ static void lnv_build(lsdm_lnv* L) {
   ws(L->wMb, L->pM);
   ws(L->wXb, L->pX);
   ws(L->wLb, L->pL);
+  if (h) ws(L->wV, L->pL);
   L->wE.alloc(sizeof(double) * 2 * DOT_BLOCKS + 64);
 }
 
@@ -335,12 +353,20 @@ static void lnv_backward(lsdm_lnv* L, double* dG, hipStream_t st) {
   T* wXb = L->wXb.as<T>();
   T* wLb = L->wLb.as<T>();
   chain_product<T>(L, 3, wX, wH, wMb, -4.0, 0.0, st);    // Mbar = X^T Pbar,  Pbar = -4H (every M strip written)
-  scatter_h<T>(L, wH, wMb, 6.0, st);                // Mbar += 3 Kbar = 6H on H's range
   chain_product<T>(L, 4, wH, wM, wXb, -4.0, 0.0, st);    // Xbar  = Pbar M
-  chain_product<T>(L, 5, wMb, wL, wXb, 1.0, 1.0, st);    // Xbar += Mbar L
-  chain_product<T>(L, 6, wX, wMb, wLb, 1.0, 0.0, st);    // Lbar  = X^T Mbar
-  chain_product<T>(L, 7, wXb, wS, wLb, 1.0, 1.0, st);    // Lbar += Xbar S
-  if (L->sym) sym_fill<T>(L->pL, wLb, st);
+  if (!L->sym) {
+    scatter_h<T>(L, wH, wMb, 6.0, st);                   // Mbar += 3 Kbar = 6H on H's range
+    chain_product<T>(L, 5, wMb, wL, wXb, 1.0, 1.0, st);  // Xbar += Mbar L
+    chain_product<T>(L, 6, wX, wMb, wLb, 1.0, 0.0, st);  // Lbar  = X^T Mbar
+    chain_product<T>(L, 7, wXb, wS, wLb, 1.0, 1.0, st);  // Lbar += Xbar S
+  } else {
+    T* wV = L->wV.as<T>();
+    chain_product<T>(L, 5, wMb, wX, wLb, 1.0, 0.0, st);  // Lbar = Mbar X = -4 X^T H X (half)
+    chain_product<T>(L, 6, wH, wX, wV, 6.0, 0.0, st);    // V = 6 H X
+    chain_product<T>(L, 7, wXb, wS, wV, 1.0, 1.0, st);   // V += Xbar S = -4 H M S
+    add_sym<T>(L->pL, wV, wLb, st);                      // Lbar += V + V^T
+    sym_fill<T>(L->pL, wLb, st);
+  }
   strip_to_user<T>(L->pL, wLb, dG, st);
   check_launch();
 }
@@ -419,14 +445,23 @@ static void lnv_backward_bf16(lsdm_lnv* L, double* dG, hipStream_t st) {
   float* wXb = L->wXb.as<float>();
   float* wLb = L->wLb.as<float>();
   chain_product_bf16(L, 3, h(XC), h(HC), wMb, -4.0, 0.0, st);   // Mbar = X^T Pbar
-  scatter_h<float>(L, wH, wMb, 6.0, st);                          // Mbar += 6H
-  to_bf16(wMb, h(MbR), h(MbC), L->pM->n_strips * 64, st);
+  if (!L->sym) scatter_h<float>(L, wH, wMb, 6.0, st);             // Mbar += 6H
+  to_bf16(wMb, h(MbR), L->sym ? nullptr : h(MbC), L->pM->n_strips * 64, st);
   chain_product_bf16(L, 4, h(HR), h(MC), wXb, -4.0, 0.0, st);   // Xbar = Pbar M
-  chain_product_bf16(L, 5, h(MbR), h(LC), wXb, 1.0, 1.0, st);   // Xbar += Mbar L
-  to_bf16(wXb, h(XbR), nullptr, L->pX->n_strips * 64, st);
-  chain_product_bf16(L, 6, h(XC), h(MbC), wLb, 1.0, 0.0, st);   // Lbar = X^T Mbar
-  chain_product_bf16(L, 7, h(XbR), h(SC), wLb, 1.0, 1.0, st);   // Lbar += Xbar S
-  if (L->sym) sym_fill<float>(L->pL, wLb, st);
+  if (!L->sym) {
+    chain_product_bf16(L, 5, h(MbR), h(LC), wXb, 1.0, 1.0, st); // Xbar += Mbar L
+    to_bf16(wXb, h(XbR), nullptr, L->pX->n_strips * 64, st);
+    chain_product_bf16(L, 6, h(XC), h(MbC), wLb, 1.0, 0.0, st); // Lbar = X^T Mbar
+    chain_product_bf16(L, 7, h(XbR), h(SC), wLb, 1.0, 1.0, st); // Lbar += Xbar S
+  } else {
+    float* wV = L->wV.as<float>();
+    to_bf16(wXb, h(XbR), nullptr, L->pX->n_strips * 64, st);
+    chain_product_bf16(L, 5, h(MbR), h(XC), wLb, 1.0, 0.0, st); // Lbar = Mbar X (half)
+    chain_product_bf16(L, 6, h(HR), h(XC), wV, 6.0, 0.0, st);   // V = 6 H X
+    chain_product_bf16(L, 7, h(XbR), h(SC), wV, 1.0, 1.0, st);  // V += Xbar S
+    add_sym<float>(L->pL, wV, wLb, st);                           // Lbar += V + V^T
+    sym_fill<float>(L->pL, wLb, st);
+  }
   strip_to_user<float>(L->pL, wLb, dG, st);
   check_launch();
 }
@@ -495,14 +530,23 @@ static void lnv_backward_rc(lsdm_lnv* L, double* dG, hipStream_t st) {
   double* wXb = L->wXb.as<double>();
   double* wLb = L->wLb.as<double>();
   rc_step(L, 3, wX, r(RX), wH, r(RH), wMb, -4.0, 0.0, st);     // Mbar = X^T Pbar
-  scatter_h<double>(L, wH, wMb, 6.0, st);                      // Mbar += 6H
+  if (!L->sym) scatter_h<double>(L, wH, wMb, 6.0, st);         // Mbar += 6H
   offsite_f32(L->pM, wMb, r(RMb), st);
   rc_step(L, 4, wH, r(RH), wM, r(RM), wXb, -4.0, 0.0, st);     // Xbar = Pbar M
-  rc_step(L, 5, wMb, r(RMb), wL, r(RL), wXb, 1.0, 1.0, st);    // Xbar += Mbar L
-  offsite_f32(L->pX, wXb, r(RXb), st);
-  rc_step(L, 6, wX, r(RX), wMb, r(RMb), wLb, 1.0, 0.0, st);    // Lbar = X^T Mbar
-  rc_step(L, 7, wXb, r(RXb), wS, r(RS), wLb, 1.0, 1.0, st);    // Lbar += Xbar S
-  if (L->sym) sym_fill<double>(L->pL, wLb, st);
+  if (!L->sym) {
+    rc_step(L, 5, wMb, r(RMb), wL, r(RL), wXb, 1.0, 1.0, st);  // Xbar += Mbar L
+    offsite_f32(L->pX, wXb, r(RXb), st);
+    rc_step(L, 6, wX, r(RX), wMb, r(RMb), wLb, 1.0, 0.0, st);  // Lbar = X^T Mbar
+    rc_step(L, 7, wXb, r(RXb), wS, r(RS), wLb, 1.0, 1.0, st);  // Lbar += Xbar S
+  } else {
+    double* wV = L->wV.as<double>();
+    offsite_f32(L->pX, wXb, r(RXb), st);
+    rc_step(L, 5, wMb, r(RMb), wX, r(RX), wLb, 1.0, 0.0, st);  // Lbar = Mbar X (half)
+    rc_step(L, 6, wH, r(RH), wX, r(RX), wV, 6.0, 0.0, st);     // V = 6 H X
+    rc_step(L, 7, wXb, r(RXb), wS, r(RS), wV, 1.0, 1.0, st);   // V += Xbar S
+    add_sym<double>(L->pL, wV, wLb, st);                         // Lbar += V + V^T
+    sym_fill<double>(L->pL, wLb, st);
+  }
   strip_to_user<double>(L->pL, wLb, dG, st);
   check_launch();
 }

@@ -16,6 +16,8 @@ template <class T> void strip_to_user(const lsdm_pattern* p, const T* strip, dou
 template <class T> void transpose_strips(const lsdm_pattern* p, const T* in, T* out, hipStream_t st);
 // the strips of a symmetric result outside keep_strip, as transposes of their mirrors
 template <class T> void sym_fill(const lsdm_pattern* p, T* data, hipStream_t st);
+// out += v + v^T (strip layout, every block of p)
+template <class T> void add_sym(const lsdm_pattern* p, const T* v, T* out, hipStream_t st);
 // C = alpha P_C(op(A) B) + beta C in strip layout (B already transposed if the plan says so)
 template <class T> void product(const lsdm_plan* pl, const T* A, const T* B, T* C, double alpha, double beta, hipStream_t st);
 // symbolic pass on the GPU: steps of a plan (count pass fill = 0, fill pass fill = 1)

@@ -74,6 +74,21 @@ __global__ void k_transpose_strips(const T* __restrict__ in, T* __restrict__ out
   }
 }
 
+// out += v + v^T in strip layout, every block of the pattern: block t of strip
+// s adds the transpose of v's block at value offset mirror[4s+t] (nothing when
+// the mirror is absent)
+template <class T>
+__global__ void k_add_sym(T* __restrict__ out, const T* __restrict__ v, const i64* __restrict__ mirror, i64 nstrips) {
+  for (i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x; g < nstrips * 64; g += (i64)gridDim.x * blockDim.x) {
+    const i64 s = g >> 6;
+    const int t = (int)((g >> 4) & 3), r = (int)((g >> 2) & 3), c = (int)(g & 3);
+    const i64 m = mirror[4 * s + t];
+    T x = v[g];
+    if (m >= 0) x += v[m + c * 4 + r];
+    out[g] += x;
+  }
+}
+
 __device__ __forceinline__ void store4(float* p, const float (&v)[4]) {
   *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
 }
@@ -1145,6 +1160,16 @@ void transpose_strips(const lsdm_pattern* p, const T* in, T* out, hipStream_t st
 }
 template void transpose_strips<double>(const lsdm_pattern*, const double*, double*, hipStream_t);
 template void transpose_strips<float>(const lsdm_pattern*, const float*, float*, hipStream_t);
+
+template <class T>
+void add_sym(const lsdm_pattern* p, const T* v, T* out, hipStream_t st) {
+  ensure_maps(const_cast<lsdm_pattern*>(p));
+  if (p->n_strips == 0) return;
+  hipLaunchKernelGGL(k_add_sym<T>, dim3(grid_for(p->n_strips * 64)), dim3(256), 0, st, out, v,
+                     p->d_mirror.as<i64>(), p->n_strips);
+}
+template void add_sym<double>(const lsdm_pattern*, const double*, double*, hipStream_t);
+template void add_sym<float>(const lsdm_pattern*, const float*, float*, hipStream_t);
 
 template <class T>
 void sym_fill(const lsdm_pattern* p, T* data, hipStream_t st) {

@@ -204,8 +204,9 @@ struct lsdm_plan {
 struct lsdm_lnv {
   const lsdm_system* sys = nullptr;
   double rS = 0, rH = 0, rL = 0;
-  // symmetric mode: L, S, H are symmetric, so M, P and dE/dL are computed on
-  // one half (F2, F3, B4, B5 half-output plans) and mirrored
+  // symmetric mode: L, S, H are symmetric, so M and P are computed on one
+  // half (F2, F3 half-output plans) and mirrored, and the adjoint takes dE/dL
+  // as V + V^T - 4 X^T H X (B3 half-output; B4, B5 make V on all of L)
   bool sym = false;
   lsdm_pattern *pS = nullptr, *pH = nullptr, *pL = nullptr, *pX = nullptr, *pM = nullptr;
   lsdm_plan *F1 = nullptr, *F2 = nullptr, *F3 = nullptr;
@@ -213,6 +214,7 @@ struct lsdm_lnv {
   lsdm::i64 max_strips = 0;
   // strip-layout workspaces (sized for FP64)
   lsdm::DevBuf wL, wS, wH, wH64, wX, wM, wP, wMb, wXb, wLb, wK;
+  lsdm::DevBuf wV;                  // symmetric mode: V = 6 H X - 4 H M S on L's pattern
   lsdm::DevBuf wE;                  // partial sums for the energy
   // map from H's strips to M's strips (K assembly and 6H into Mbar)
   lsdm::DevBuf d_h2m;               // i64 per H strip: M strip index
