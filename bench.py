@@ -273,7 +273,7 @@ def main():
     achieved = tot_fl / (tot_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.prec]
     per_product = {k: {"avg_ms": round(v[0] / max(v[1], 1), 4), "tflops": round(v[1] * v[2] / max(v[0], 1e-12) / 1e9, 2)}
-                   for k, v in rec.items()}
+                   for k, v in rec.items() if v[1] > 0}
     log(f"[bench] product kernels: {launches} launches, {tot_ms / args.profile_steps:.3f} ms/step, "
         f"{achieved:.2f} TFLOP/s useful; {per_product}")
 
