@@ -1,0 +1,110 @@
+"""The symmetric-mode adjoint of the GPU chain, assembled from the oracle's
+plain truncated products (CPU): with S, H, L symmetric the gradient of eq. 3
+is taken as
+
+    Mbar = -4 P_M(X^T H),  Xbar = -4 P_X(H M),
+    dE/dL = P_L(Mbar X) + V + V^T,   V = 6 P_L(H X) + P_L(Xbar S),
+
+with X = P_X(L S) and M = P_M(X L) on the chain's ranges.  Every truncation
+has to keep what L's range reaches for this to equal the gradient of eq. 3;
+the cases include R_L > R_H, where M's range R_H + R_L + R_S is shorter than
+the natural range of LSL, images of a small periodic cell, ragged blocks and
+an open cluster.  The comparison is against the oracle's own gradient, which
+groups the terms another way (6 (HX + (HX)^T) - 4 (H XX + (H XX)^T + X^T H X)).
+
+The energy identity used when comparing energy routes is pinned as well:
+<P_H(X M), H> = <M, P_M(X^T H)> (the same triple sum in another order)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+CASES = {
+    "si64_rl12": lambda: (workloads.diamond(2), 8.0, 12.0, 12.0),
+    "si8_cell_images": lambda: (workloads.diamond(1), 8.0, 12.0, 12.0),
+    "si64_jitter_rl16": lambda: (workloads.diamond(2, jitter=0.1, seed=7), 8.0, 12.0, 16.0),
+    "open_cluster_ragged": lambda: (workloads.random_cluster(60, 12.0, nfn=np.arange(60) % 5 + 1, seed=9),
+                                    5.0, 6.0, 6.5),
+    "mixed_box_13_5": lambda: (workloads.random_box(120, 14.0, 96, 13, 5, seed=3), 6.0, 8.0, 8.0),
+}
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _grouped(L, S, H, pX, pM, pXbar=None, pMbar=None):
+    """dE/dL by the symmetric-mode grouping; pXbar / pMbar override the
+    patterns of Xbar and Mbar (to show that shorter ranges are detected)."""
+    pL = L.pattern
+    X = oracle.multiply(L, S, pX)
+    M = oracle.multiply(X, L, pM)
+    Mbar = oracle.multiply(oracle.transpose(X, pX), H, pMbar or pM)
+    Mbar.val *= -4.0
+    Xbar = oracle.multiply(H, M, pXbar or pX)
+    Xbar.val *= -4.0
+    B3 = oracle.multiply(Mbar, X, pL)
+    V = oracle.multiply(H, X, pL)
+    V.val *= 6.0
+    oracle.multiply(Xbar, S, pL, out=V)
+    return B3.val, V.val, oracle.transpose(V, pL).val
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_symmetric_adjoint_grouping_equals_gradient(name):
+    s, rS, rH, rL = CASES[name]()
+    R = oracle.chain_ranges(rS, rH, rL)
+    inp = oracle.make_inputs(s, rS, rH, rL)
+    L, S, H = inp["L"], inp["S"], inp["H"]
+    pX, pM = oracle.pattern(s, R["X"]), oracle.pattern(s, R["M"])
+    B3, V, VT = _grouped(L, S, H, pX, pM)
+    Gref = oracle.lnv_gradient(L, S, H, rS, rH, rL)
+    assert _rel(B3 + V + VT, Gref.val) <= 1e-13, _rel(B3 + V + VT, Gref.val)
+    # the grouping is not an identity of arbitrary matrices: dropping the
+    # transposed half of V breaks it
+    assert _rel(B3 + 2.0 * V, Gref.val) > 1e-3
+
+
+def _sym_random(p, rng):
+    A = oracle.Matrix(p, rng.standard_normal(p.nval))
+    return oracle.Matrix(p, 0.5 * (A.val + oracle.transpose(A, p).val))
+
+
+@pytest.mark.parametrize("name", ["si64_jitter_rl16", "open_cluster_ragged"])
+def test_symmetric_adjoint_ranges_without_decay(name):
+    """Symmetric values of unit size at every range (no decay with distance),
+    so that an element dropped by a short range shows: the chain's ranges give
+    the gradient to rounding; Xbar or Mbar on a range 4 bohr shorter do not
+    (4 bohr spans a shell of the crystal's pair distances)."""
+    s, rS, rH, rL = CASES[name]()
+    R = oracle.chain_ranges(rS, rH, rL)
+    rng = np.random.default_rng(5)
+    L, S, H = (_sym_random(oracle.pattern(s, r), rng) for r in (rL, rS, rH))
+    pX, pM = oracle.pattern(s, R["X"]), oracle.pattern(s, R["M"])
+    Gref = oracle.lnv_gradient(L, S, H, rS, rH, rL).val
+    assert _rel(sum(_grouped(L, S, H, pX, pM)), Gref) <= 1e-13
+    short_x = _grouped(L, S, H, pX, pM, pXbar=oracle.pattern(s, R["X"] - 4.0))
+    short_m = _grouped(L, S, H, pX, pM, pMbar=oracle.pattern(s, R["M"] - 4.0))
+    assert _rel(sum(short_x), Gref) > 1e-6
+    assert _rel(sum(short_m), Gref) > 1e-6
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_energy_trace_identity(name):
+    s, rS, rH, rL = CASES[name]()
+    R = oracle.chain_ranges(rS, rH, rL)
+    inp = oracle.make_inputs(s, rS, rH, rL)
+    L, S, H = inp["L"], inp["S"], inp["H"]
+    pX, pM = oracle.pattern(s, R["X"]), oracle.pattern(s, R["M"])
+    X = oracle.multiply(L, S, pX)
+    M = oracle.multiply(X, L, pM)
+    P = oracle.multiply(X, M, H.pattern)
+    Y = oracle.multiply(oracle.transpose(X, pX), H, pM)
+    a = oracle.dot(P.val, H.val)
+    b = oracle.dot(M.val, Y.val)
+    assert abs(a - b) <= 1e-13 * max(abs(a), 1.0), (a, b)
+    # and E = 6 <M|_H, H> - 4 <P, H> is the oracle's energy
+    E = 6.0 * oracle.dot(oracle.project(M, H.pattern).val, H.val) - 4.0 * a
+    Eref = oracle.lnv_energy(L, S, H, rS, rH, rL)["E"]
+    assert abs(E - Eref) <= 1e-13 * abs(Eref), (E, Eref)
