@@ -243,7 +243,10 @@ int lsdm_lnv_purify(lsdm_lnv* lnv, int prec, const double* dL, const double* dS,
 int lsdm_lnv_profile(lsdm_lnv* lnv, int enable);
 /* Waits for the recorded events, then returns per product (F1 F2 F3 B1 B2 B3
  * B4 B5; host arrays of 8) the summed kernel milliseconds, the number of
- * launches and the useful flops of one launch; clears the record. */
+ * launches and the useful flops of one launch; clears the record.  F1-F3 make
+ * X = LS, M = XL and P = XM; B1 Mbar = X^T Pbar, B2 Xbar = Pbar M, then
+ * B3 Xbar += Mbar L, B4 dE/dL = X^T Mbar, B5 dE/dL += Xbar S, or in symmetric
+ * mode B3 dE/dL = Mbar X, B4 V = 6 HX, B5 V += Xbar S (dE/dL += V + V^T). */
 int lsdm_lnv_profile_read(lsdm_lnv* lnv, double* ms, int64_t* launches, double* flops);
 void lsdm_lnv_destroy(lsdm_lnv* lnv);
 

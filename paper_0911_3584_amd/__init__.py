@@ -168,7 +168,9 @@ class LNV:
 
     def __init__(self, system, rS, rH, rL, symmetric=False):
         """symmetric=True: L, S and H are symmetric (every L passed later too);
-        M, P and dE/dL are then computed on one half and mirrored."""
+        M, P and the X^T H X term of dE/dL are then computed on one half and
+        mirrored, and dE/dL is assembled as V + V^T - 4 X^T H X with
+        V = 6 HX - 4 HMS (the gradient's terms, regrouped)."""
         h = ctypes.c_void_p()
         check(lib().lsdm_lnv_create_ex(system._h, float(rS), float(rH), float(rL),
                                        self.SYMMETRIC if symmetric else 0, ctypes.byref(h)))
