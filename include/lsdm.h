@@ -81,7 +81,8 @@ enum {
  * xyz: host, 3*n_atoms doubles.  nfn: host, n_atoms values in 1..16.
  * lattice: host, 9 doubles (rows are the translation vectors) or NULL.
  * Positions must be finite; periodic positions may lie outside the cell.
- * Errors: LSDM_EINVAL. */
+ * Errors: LSDM_EINVAL (n_atoms < 1, a null pointer, a non-finite position,
+ * nfn outside 1..16, a singular lattice). */
 int lsdm_system_create(int32_t n_atoms, const double* xyz, const int32_t* nfn,
                        const double* lattice, lsdm_system** out);
 void lsdm_system_destroy(lsdm_system* sys);
