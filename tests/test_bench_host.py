@@ -44,3 +44,19 @@ def test_summarize_pmc_needs_the_calibration_copy(tmp_path):
     _write(tmp_path / "w", "WRITE_SIZE", [(2, prod, 200.0)])
     with pytest.raises(SystemExit):
         bench.summarize_pmc(str(tmp_path / "f"), str(tmp_path / "w"), "fp32", str(tmp_path / "t.json"))
+
+
+def test_traffic_reported_only_for_matching_sources(tmp_path, monkeypatch):
+    f = tmp_path / "traffic.json"
+    summ = {"kernel_hash": bench.kernel_hash(), "prec": "fp32", "steps": 1,
+            "dispatches": [{"fetch_bytes": 3.0e9, "write_bytes": 1.0e9}, {"fetch_bytes": 2.0e9, "write_bytes": 0.5e9}]}
+    f.write_text(json.dumps(summ))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    wl = bench.DEFAULT_WORKLOAD
+    assert bench.traffic_per_step("fp32", wl) == pytest.approx(6.5e9)
+    assert bench.traffic_per_step("fp64", wl) is None                  # another precision
+    assert bench.traffic_per_step("fp32", "mixed8000_rl14") is None    # another workload
+    summ["kernel_hash"] = "0" * 16                                       # sources changed since
+    f.write_text(json.dumps(summ))
+    assert bench.traffic_per_step("fp32", wl) is None
+
