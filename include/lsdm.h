@@ -30,14 +30,17 @@
  *   Ownership: handles are created and destroyed by the library; value
  *     buffers belong to the caller and are never freed by the library.  Device
  *     workspace is allocated by the library (hipMalloc) when a handle is
- *     created and released when it is destroyed.
+ *     created or first used and released when it is destroyed: a plan keeps
+ *     the operand workspaces of its stand-alone multiplies and the two plans
+ *     of its adjoint, so repeated calls on one plan allocate nothing.
  *   Streams: compute calls enqueue work on `stream` (a hipStream_t, NULL = the
- *     default stream).  The LNV energy, gradient, shift and electron calls
- *     return without waiting; *_create calls, the stand-alone multiplies (which
- *     release their workspaces), the line search and the minimiser (which read
- *     scalars back) synchronise, and so does the first call that builds a lazy
- *     map of a handle (transposes, residual-mode maps, the S-in-H map).  Calls
- *     on one handle must not run concurrently, on one stream or several.
+ *     default stream).  The multiplies and the LNV energy, gradient, shift and
+ *     electron calls return without waiting; *_create calls, lsdm_dot, the
+ *     line search and the minimiser (which read scalars back or release
+ *     buffers) synchronise, and so does the first call that builds a lazy
+ *     part of a handle (layout maps, adjoint plans, residual-mode maps, the
+ *     S-in-H map).  Calls on one handle must not run concurrently, on one
+ *     stream or several: they share the handle's workspaces.
  *   Errors: every call returns LSDM_OK (0) or a negative status; no exception
  *     crosses the ABI; lsdm_last_error() returns a message for the calling
  *     thread's last failure.  A failed call leaves its outputs undefined and
@@ -125,6 +128,9 @@ void lsdm_plan_destroy(lsdm_plan* plan);
 
 /* C = alpha P_C(op(A) op(B)) + beta C, values in block layout on device.
  * dA, dB, dC: device doubles on the patterns given to lsdm_plan_create.
+ * Asynchronous on the stream; the plan keeps the strip-layout copies of the
+ * operands it needs (allocated on the first call in a precision), so calls
+ * on one plan must be ordered (one stream, or synchronised between them).
  * prec: LSDM_FP64, LSDM_FP32, LSDM_BF16 or LSDM_FP32_RC.  In FP32_RC mode each
  * operand is split into its on-site blocks D (i = j, n = 0) and the rest R, and
  * AB = D_A B + A D_B - D_A D_B (FP64, block-diagonal scalings) + R_A R_B (FP32).
@@ -132,12 +138,14 @@ void lsdm_plan_destroy(lsdm_plan* plan);
 int lsdm_multiply(const lsdm_plan* plan, int prec, double alpha, const double* dA, const double* dB,
                   double beta, double* dC, void* stream);
 
-/* Adjoint of the truncated product: for C = P_C(op(A) op(B)) and an upstream
- * gradient dCbar on C's pattern,
+/* Adjoint of the truncated product (the derivative of the multiply above):
+ * for C = P_C(op(A) op(B)) and an upstream gradient dCbar on C's pattern,
  *   dAbar += P_A(Cbar op(B)^T)   (P_A(op(B) Cbar^T) when A enters transposed)
  *   dBbar += P_B(op(A)^T Cbar)   (P_B(Cbar^T op(A)) when B enters transposed)
  * Either output may be NULL (not computed).  Both accumulate.  Every
- * precision mode.  Errors: LSDM_EINVAL, LSDM_EDEVICE. */
+ * precision mode.  The two products' plans are built on the first call that
+ * needs them (synchronous) and kept by the plan; later calls are
+ * asynchronous.  Errors: LSDM_EINVAL, LSDM_ENOMEM, LSDM_EDEVICE. */
 int lsdm_multiply_adjoint(const lsdm_plan* plan, int prec, const double* dCbar, const double* dA,
                           const double* dB, double* dAbar, double* dBbar, void* stream);
 
@@ -151,7 +159,9 @@ int lsdm_dot(const lsdm_pattern* p, const double* dA, const double* dB, double* 
  * X = LS (rL + rS), M = LSL (min(2 rL + rS, rH + rL + rS)) and every plan of
  * the forward and adjoint chains.  These ranges drop only elements that cannot
  * reach K on H's range or dE/dL on L's range, so E and dE/dL equal the
- * untruncated algebra restricted to the S, H and L patterns.
+ * untruncated algebra restricted to the S, H and L patterns.  Any ranges are
+ * accepted; where rH > 2 rL + rS, LSL is zero on the blocks of H beyond its
+ * range and K = -2 LSLSL there.
  * Errors: LSDM_EINVAL (a range < 0), LSDM_ENOMEM, LSDM_EDEVICE. */
 int lsdm_lnv_create(const lsdm_system* sys, double rS, double rH, double rL, lsdm_lnv** out);
 /* Flags of lsdm_lnv_create_ex. */

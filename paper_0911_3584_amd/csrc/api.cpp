@@ -130,104 +130,107 @@ static lsdm_plan* make_plan(const lsdm_pattern* A, int tA, const lsdm_pattern* B
 
 static size_t strip_bytes(const lsdm_pattern* p, size_t elem) { return (size_t)p->n_strips * 64 * elem + 64; }
 
-// workspaces of a stand-alone multiply: strip copies of A, B (and B^T), C
-struct MulWork {
-  DevBuf a, b, bt, c;
-};
+// Workspace slot k of a plan's stand-alone multiplies, at least `bytes` long:
+// allocated on first use and grown when a wider precision needs more, then
+// kept with the plan (calls on one plan are ordered on their stream, so the
+// same buffers serve every call).
+enum { MW_A, MW_B, MW_BT, MW_C, MW_A2, MW_B2, MW_C2 };
+template <class T>
+static T* plan_ws(const lsdm_plan* cpl, int k, const lsdm_pattern* p, size_t elem) {
+  lsdm_plan* pl = const_cast<lsdm_plan*>(cpl);
+  std::lock_guard<std::mutex> g(pl->mw_mutex);
+  const size_t need = strip_bytes(p, elem);
+  if (pl->mw[k].bytes < need) pl->mw[k].alloc(need);
+  return pl->mw[k].as<T>();
+}
 
 template <class T>
 static void multiply_t(const lsdm_plan* pl, double alpha, const double* dA, const double* dB, double beta, double* dC,
                        hipStream_t st) {
-  MulWork w;
-  w.a.alloc(strip_bytes(pl->A, sizeof(T)));
-  w.b.alloc(strip_bytes(pl->B, sizeof(T)));
-  w.c.alloc(strip_bytes(pl->C, sizeof(T)));
-  fill<T>(w.a.as<T>(), pl->A->n_strips * 64, (T)0, st);
-  fill<T>(w.b.as<T>(), pl->B->n_strips * 64, (T)0, st);
-  fill<T>(w.c.as<T>(), pl->C->n_strips * 64, (T)0, st);
-  user_to_strip<T>(pl->A, dA, w.a.as<T>(), 1.0, st);
-  user_to_strip<T>(pl->B, dB, w.b.as<T>(), 1.0, st);
-  const T* Bop = w.b.as<T>();
+  T* a = plan_ws<T>(pl, MW_A, pl->A, sizeof(T));
+  T* b = plan_ws<T>(pl, MW_B, pl->B, sizeof(T));
+  T* c = plan_ws<T>(pl, MW_C, pl->C, sizeof(T));
+  fill<T>(a, pl->A->n_strips * 64, (T)0, st);
+  fill<T>(b, pl->B->n_strips * 64, (T)0, st);
+  fill<T>(c, pl->C->n_strips * 64, (T)0, st);
+  user_to_strip<T>(pl->A, dA, a, 1.0, st);
+  user_to_strip<T>(pl->B, dB, b, 1.0, st);
+  const T* Bop = b;
   if (pl->transB) {
-    w.bt.alloc(strip_bytes(pl->B, sizeof(T)));
-    transpose_strips<T>(pl->B, w.b.as<T>(), w.bt.as<T>(), st);
-    Bop = w.bt.as<T>();
+    T* bt = plan_ws<T>(pl, MW_BT, pl->B, sizeof(T));
+    transpose_strips<T>(pl->B, b, bt, st);
+    Bop = bt;
   }
-  if (beta != 0.0) user_to_strip<T>(pl->C, dC, w.c.as<T>(), 1.0, st);
-  product<T>(pl, w.a.as<T>(), Bop, w.c.as<T>(), alpha, beta, st);
-  strip_to_user<T>(pl->C, w.c.as<T>(), dC, st);
+  if (beta != 0.0) user_to_strip<T>(pl->C, dC, c, 1.0, st);
+  product<T>(pl, a, Bop, c, alpha, beta, st);
+  strip_to_user<T>(pl->C, c, dC, st);
   check_launch();
-  HIP_CHECK(hipStreamSynchronize(st));   // the workspaces are released on return
 }
 
 static void multiply_bf16(const lsdm_plan* pl, double alpha, const double* dA, const double* dB, double beta,
                           double* dC, hipStream_t st) {
   typedef unsigned short u16;
-  DevBuf a32, b32, bt32, c32, a16, b16;
-  a32.alloc(strip_bytes(pl->A, 4));
-  b32.alloc(strip_bytes(pl->B, 4));
-  c32.alloc(strip_bytes(pl->C, 4));
-  a16.alloc(strip_bytes(pl->A, 2));
-  b16.alloc(strip_bytes(pl->B, 2));
-  fill<float>(a32.as<float>(), pl->A->n_strips * 64, 0.f, st);
-  fill<float>(b32.as<float>(), pl->B->n_strips * 64, 0.f, st);
-  fill<float>(c32.as<float>(), pl->C->n_strips * 64, 0.f, st);
-  user_to_strip<float>(pl->A, dA, a32.as<float>(), 1.0, st);
-  user_to_strip<float>(pl->B, dB, b32.as<float>(), 1.0, st);
+  float* a32 = plan_ws<float>(pl, MW_A, pl->A, 4);
+  float* b32 = plan_ws<float>(pl, MW_B, pl->B, 4);
+  float* c32 = plan_ws<float>(pl, MW_C, pl->C, 4);
+  u16* a16 = plan_ws<u16>(pl, MW_A2, pl->A, 2);
+  u16* b16 = plan_ws<u16>(pl, MW_B2, pl->B, 2);
+  fill<float>(a32, pl->A->n_strips * 64, 0.f, st);
+  fill<float>(b32, pl->B->n_strips * 64, 0.f, st);
+  fill<float>(c32, pl->C->n_strips * 64, 0.f, st);
+  user_to_strip<float>(pl->A, dA, a32, 1.0, st);
+  user_to_strip<float>(pl->B, dB, b32, 1.0, st);
   // A: row-major copy, or for a transposed A the block-transposed copy of A
-  to_bf16(a32.as<float>(), pl->transA ? nullptr : a16.as<u16>(), pl->transA ? a16.as<u16>() : nullptr,
-          pl->A->n_strips * 64, st);
-  const float* bsrc = b32.as<float>();
+  to_bf16(a32, pl->transA ? nullptr : a16, pl->transA ? a16 : nullptr, pl->A->n_strips * 64, st);
+  const float* bsrc = b32;
   if (pl->transB) {
-    bt32.alloc(strip_bytes(pl->B, 4));
-    transpose_strips<float>(pl->B, b32.as<float>(), bt32.as<float>(), st);
-    bsrc = bt32.as<float>();
+    float* bt32 = plan_ws<float>(pl, MW_BT, pl->B, 4);
+    transpose_strips<float>(pl->B, b32, bt32, st);
+    bsrc = bt32;
   }
-  to_bf16(bsrc, nullptr, b16.as<u16>(), pl->B->n_strips * 64, st);
-  if (beta != 0.0) user_to_strip<float>(pl->C, dC, c32.as<float>(), 1.0, st);
-  product_bf16(pl, a16.as<u16>(), b16.as<u16>(), c32.as<float>(), alpha, beta, st);
-  strip_to_user<float>(pl->C, c32.as<float>(), dC, st);
+  to_bf16(bsrc, nullptr, b16, pl->B->n_strips * 64, st);
+  if (beta != 0.0) user_to_strip<float>(pl->C, dC, c32, 1.0, st);
+  product_bf16(pl, a16, b16, c32, alpha, beta, st);
+  strip_to_user<float>(pl->C, c32, dC, st);
   check_launch();
-  HIP_CHECK(hipStreamSynchronize(st));
 }
 
 // residual mode: FP64 master strips; FP32 product of the off-site parts; FP64
 // block-diagonal correction
 static void multiply_rc(const lsdm_plan* pl, double alpha, const double* dA, const double* dB, double beta, double* dC,
                         hipStream_t st) {
-  DevBuf a64, b64, bt64, c64, a32, b32, rr;
-  a64.alloc(strip_bytes(pl->A, 8));
-  b64.alloc(strip_bytes(pl->B, 8));
-  c64.alloc(strip_bytes(pl->C, 8));
-  a32.alloc(strip_bytes(pl->A, 4));
-  b32.alloc(strip_bytes(pl->B, 4));
-  rr.alloc(strip_bytes(pl->C, 4));
-  fill<double>(a64.as<double>(), pl->A->n_strips * 64, 0.0, st);
-  fill<double>(b64.as<double>(), pl->B->n_strips * 64, 0.0, st);
-  fill<double>(c64.as<double>(), pl->C->n_strips * 64, 0.0, st);
-  user_to_strip<double>(pl->A, dA, a64.as<double>(), 1.0, st);
-  user_to_strip<double>(pl->B, dB, b64.as<double>(), 1.0, st);
-  const double* bsrc = b64.as<double>();
+  double* a64 = plan_ws<double>(pl, MW_A, pl->A, 8);
+  double* b64 = plan_ws<double>(pl, MW_B, pl->B, 8);
+  double* c64 = plan_ws<double>(pl, MW_C, pl->C, 8);
+  float* a32 = plan_ws<float>(pl, MW_A2, pl->A, 4);
+  float* b32 = plan_ws<float>(pl, MW_B2, pl->B, 4);
+  float* rr = plan_ws<float>(pl, MW_C2, pl->C, 4);
+  fill<double>(a64, pl->A->n_strips * 64, 0.0, st);
+  fill<double>(b64, pl->B->n_strips * 64, 0.0, st);
+  fill<double>(c64, pl->C->n_strips * 64, 0.0, st);
+  user_to_strip<double>(pl->A, dA, a64, 1.0, st);
+  user_to_strip<double>(pl->B, dB, b64, 1.0, st);
+  const double* bsrc = b64;
   if (pl->transB) {
-    bt64.alloc(strip_bytes(pl->B, 8));
-    transpose_strips<double>(pl->B, b64.as<double>(), bt64.as<double>(), st);
-    bsrc = bt64.as<double>();
+    double* bt64 = plan_ws<double>(pl, MW_BT, pl->B, 8);
+    transpose_strips<double>(pl->B, b64, bt64, st);
+    bsrc = bt64;
   }
-  offsite_f32(pl->A, a64.as<double>(), a32.as<float>(), st);
-  offsite_f32(pl->B, bsrc, b32.as<float>(), st);
-  if (beta != 0.0) user_to_strip<double>(pl->C, dC, c64.as<double>(), 1.0, st);
-  product<float>(pl, a32.as<float>(), b32.as<float>(), rr.as<float>(), 1.0, 0.0, st);
-  rc_correct(pl, a64.as<double>(), bsrc, rr.as<float>(), c64.as<double>(), alpha, beta, st);
-  strip_to_user<double>(pl->C, c64.as<double>(), dC, st);
+  offsite_f32(pl->A, a64, a32, st);
+  offsite_f32(pl->B, bsrc, b32, st);
+  if (beta != 0.0) user_to_strip<double>(pl->C, dC, c64, 1.0, st);
+  product<float>(pl, a32, b32, rr, 1.0, 0.0, st);
+  rc_correct(pl, a64, bsrc, rr, c64, alpha, beta, st);
+  strip_to_user<double>(pl->C, c64, dC, st);
   check_launch();
-  HIP_CHECK(hipStreamSynchronize(st));
 }
 
 // ---------------------------------------------------------------------------
 // the LNV chain
 // ---------------------------------------------------------------------------
 // for every strip of `from`, the strip of `to` with the same (row, column
-// quad, image); `to` must contain `from`
+// quad, image); a strip `to` lacks maps to -1 when `what` is null, else it is
+// an error (`to` must contain `from`)
 static std::vector<i64> strip_map(const lsdm_system* sys, const lsdm_pattern* from, const lsdm_pattern* to,
                                   const char* what) {
   std::vector<i64> map(from->n_strips, -1);
@@ -236,7 +239,10 @@ static std::vector<i64> strip_map(const lsdm_system* sys, const lsdm_pattern* fr
     for (i64 h = from->sptr[q]; h < from->sptr[q + 1]; ++h) {
       const i64 key = skey(from->squad[h], from->simg[h]);
       while (m < to->sptr[q + 1] && skey(to->squad[m], to->simg[m]) < key) ++m;
-      if (m >= to->sptr[q + 1] || skey(to->squad[m], to->simg[m]) != key) LSDM_THROW(LSDM_EPATTERN, what);
+      if (m >= to->sptr[q + 1] || skey(to->squad[m], to->simg[m]) != key) {
+        if (what) LSDM_THROW(LSDM_EPATTERN, what);
+        continue;
+      }
       map[h] = m;
     }
   }
@@ -267,9 +273,10 @@ static void lnv_build(lsdm_lnv* L) {
     L->B4 = make_plan(L->pX, 1, L->pM, 0, L->pL);
   }
   L->B5 = make_plan(L->pX, 0, L->pS, 0, L->pL);
-  // H strip -> M strip with the same (row, column quad, image); M's range
-  // contains H's, so every H strip has one
-  const std::vector<i64> h2m = strip_map(L->sys, L->pH, L->pM, "H range exceeds the LSL range");
+  // H strip -> M strip with the same (row, column quad, image), -1 where M
+  // has none: when rH > 2 rL + rS, LSL is zero beyond its own range, so those
+  // blocks of K are -2 P alone and carry no 6H into Mbar
+  const std::vector<i64> h2m = strip_map(L->sys, L->pH, L->pM, nullptr);
   L->d_h2m.upload(h2m.data(), sizeof(i64) * h2m.size());
   auto ws = [](DevBuf& b, const lsdm_pattern* p) { b.alloc(strip_bytes(p, sizeof(double))); };
   ws(L->wL, L->pL);
@@ -605,6 +612,11 @@ static void purify_chain(lsdm_lnv* L, const double* dL, const double* dS, double
 
 }  // namespace lsdm
 
+lsdm_plan::~lsdm_plan() {
+  delete adjA;
+  delete adjB;
+}
+
 lsdm_lnv::~lsdm_lnv() {
   for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
 }
@@ -725,19 +737,28 @@ int lsdm_multiply_adjoint(const lsdm_plan* pl, int prec, const double* dCbar, co
       else if (prec == LSDM_BF16) multiply_bf16(q, 1.0, x, y, 1.0, out, st);
       else multiply_rc(q, 1.0, x, y, 1.0, out, st);
     };
+    lsdm_plan* mp = const_cast<lsdm_plan*>(pl);
     if (dAbar) {
       // Abar += P_A(Cbar op(B)^T), or P_A(op(B) Cbar^T) when A enters transposed
-      std::unique_ptr<lsdm_plan> q(pl->transA ? make_plan(pl->B, pl->transB, pl->C, 1, pl->A)
-                                               : make_plan(pl->C, 0, pl->B, !pl->transB, pl->A));
-      if (pl->transA) run(q.get(), dB, dCbar, dAbar);
-      else run(q.get(), dCbar, dB, dAbar);
+      {
+        std::lock_guard<std::mutex> g(mp->adj_mutex);
+        if (!mp->adjA)
+          mp->adjA = pl->transA ? make_plan(pl->B, pl->transB, pl->C, 1, pl->A)
+                                : make_plan(pl->C, 0, pl->B, !pl->transB, pl->A);
+      }
+      if (pl->transA) run(mp->adjA, dB, dCbar, dAbar);
+      else run(mp->adjA, dCbar, dB, dAbar);
     }
     if (dBbar) {
       // Bbar += P_B(op(A)^T Cbar), or P_B(Cbar^T op(A)) when B enters transposed
-      std::unique_ptr<lsdm_plan> q(pl->transB ? make_plan(pl->C, 1, pl->A, pl->transA, pl->B)
-                                               : make_plan(pl->A, !pl->transA, pl->C, 0, pl->B));
-      if (pl->transB) run(q.get(), dCbar, dA, dBbar);
-      else run(q.get(), dA, dCbar, dBbar);
+      {
+        std::lock_guard<std::mutex> g(mp->adj_mutex);
+        if (!mp->adjB)
+          mp->adjB = pl->transB ? make_plan(pl->C, 1, pl->A, pl->transA, pl->B)
+                                : make_plan(pl->A, !pl->transA, pl->C, 0, pl->B);
+      }
+      if (pl->transB) run(mp->adjB, dCbar, dA, dBbar);
+      else run(mp->adjB, dA, dCbar, dBbar);
     }
   });
 }

@@ -171,7 +171,11 @@ __global__ void k_to_bf16(const float* __restrict__ in, unsigned short* __restri
 // quad; the slot bits of an entry are OR-ed over its GJ lanes, active entries
 // become steps in inner-list order.  Count pass: steps per tile and the useful
 // work (integer atomics, so the totals are exact and order independent).  Fill
-// pass: writes the step records from the tile's first step.
+// pass: writes the step records from the tile's first step.  A step names
+// only the operands it uses: a B strip whose column quad has no active slot,
+// and an A block whose row has none, are recorded as absent (-1), so the
+// product kernels do not fetch them (they could only meet masked outputs or
+// zero blocks).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_plan_gsteps(const GTile* __restrict__ tiles, i64 ntiles,
                                                      const GKEnt* __restrict__ kent, const i64* __restrict__ kbeg,
@@ -197,6 +201,9 @@ __global__ void __launch_bounds__(256) k_plan_gsteps(const GTile* __restrict__ t
 #pragma unroll
       for (int w = 0; w < GQ; ++w) m[w] = 0;
       if (e < ke) gslot_work(v, tl, kent[e], jq, ck, &b, m, &fl, &tr);
+      // this lane's column has an active slot: its B strip is used
+      if ((m[0] | m[1] | m[2] | m[3]) == 0u) b = -1;
+      static_assert(GQ == 4, "column activity test");
       uint32_t any = 0;
 #pragma unroll
       for (int w = 0; w < GQ; ++w) {
@@ -216,8 +223,11 @@ __global__ void __launch_bounds__(256) k_plan_gsteps(const GTile* __restrict__ t
           uint32_t rows = 0;
 #pragma unroll
           for (int r = 0; r < GROWS; ++r) {
-            sp[r] = ent.a[r];
-            rows |= (ent.a[r] >= 0 ? 1u : 0u) << r;
+            // the row has an active slot in some column quad: its A block is used
+            const bool used = ((m[r >> 2] >> (GJ * (r & 3))) & ((1u << GJ) - 1u)) != 0u;
+            const i32 a = used ? ent.a[r] : -1;
+            sp[r] = a;
+            rows |= (a >= 0 ? 1u : 0u) << r;
           }
 #pragma unroll
           for (int w = 0; w < GQ; ++w) sp[GROWS + GJ + w] = (int)m[w];
@@ -1030,7 +1040,8 @@ __global__ void k_rc_apply(const uint8_t* __restrict__ cmask, const i32* __restr
 }
 
 // ---------------------------------------------------------------------------
-// K = 3 M|_H - 2 P on H's strips (FP64), masked to H's pattern
+// K = 3 M|_H - 2 P on H's strips (FP64), masked to H's pattern; an H strip
+// outside M's pattern (h2m = -1: beyond the range of LSL) takes M as zero
 // ---------------------------------------------------------------------------
 template <class T>
 __global__ void k_kassembly(const T* __restrict__ M, const T* __restrict__ P, double* __restrict__ K,
@@ -1039,17 +1050,23 @@ __global__ void k_kassembly(const T* __restrict__ M, const T* __restrict__ P, do
     const i64 h = g >> 6;
     const int e = (int)(g & 63), t = e >> 4;
     const bool in = (hmask[h] >> t) & 1;
-    K[g] = in ? 3.0 * (double)M[h2m[h] * 64 + e] - 2.0 * (double)P[g] : 0.0;
+    const i64 m = h2m[h];
+    const double mv = m >= 0 ? (double)M[m * 64 + e] : 0.0;
+    K[g] = in ? 3.0 * mv - 2.0 * (double)P[g] : 0.0;
   }
 }
 
-// Mbar += scale * H on H's blocks (H's strips mapped into M's strips)
+// Mbar += scale * H on the blocks of H inside M's pattern (H's strips mapped
+// into M's strips; blocks outside M's, which LSL cannot reach, are skipped,
+// so Mbar stays zero off its pattern)
 template <class T>
-__global__ void k_scatter_h(const T* __restrict__ H, T* __restrict__ Mb, const i64* __restrict__ h2m, i64 nh, T scale) {
+__global__ void k_scatter_h(const T* __restrict__ H, T* __restrict__ Mb, const i64* __restrict__ h2m,
+                            const uint8_t* __restrict__ mmask, i64 nh, T scale) {
   for (i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x; g < nh * 64; g += (i64)gridDim.x * blockDim.x) {
     const i64 h = g >> 6;
     const int e = (int)(g & 63);
-    Mb[h2m[h] * 64 + e] += scale * H[g];
+    const i64 m = h2m[h];
+    if (m >= 0 && ((mmask[m] >> (e >> 4)) & 1)) Mb[m * 64 + e] += scale * H[g];
   }
 }
 
@@ -1362,7 +1379,8 @@ template <class T>
 void scatter_h(const lsdm_lnv* L, const T* H, T* Mb, double scale, hipStream_t st) {
   const i64 nh = L->pH->n_strips;
   if (nh == 0) return;
-  hipLaunchKernelGGL(k_scatter_h<T>, dim3(grid_for(nh * 64)), dim3(256), 0, st, H, Mb, L->d_h2m.as<i64>(), nh, (T)scale);
+  hipLaunchKernelGGL(k_scatter_h<T>, dim3(grid_for(nh * 64)), dim3(256), 0, st, H, Mb, L->d_h2m.as<i64>(),
+                     L->pM->d_smask.as<uint8_t>(), nh, (T)scale);
 }
 template void scatter_h<double>(const lsdm_lnv*, const double*, double*, double, hipStream_t);
 template void scatter_h<float>(const lsdm_lnv*, const float*, float*, double, hipStream_t);

@@ -199,6 +199,15 @@ struct lsdm_plan {
   std::mutex rc_mutex;
   // for a transposed B the plan multiplies by a materialised transpose
   lsdm::DevBuf d_bT;                // strip-layout workspace of B^T (doubles)
+  // stand-alone multiplies: strip-layout workspaces of the operands (grown on
+  // first use in a precision, then kept), and the two plans of the adjoint
+  // (built on first use), so repeated calls allocate and plan nothing
+  lsdm::DevBuf mw[8];
+  std::mutex mw_mutex;
+  lsdm_plan* adjA = nullptr;        // plan of Abar += P_A(...)
+  lsdm_plan* adjB = nullptr;        // plan of Bbar += P_B(...)
+  std::mutex adj_mutex;
+  ~lsdm_plan();
 };
 
 struct lsdm_lnv {

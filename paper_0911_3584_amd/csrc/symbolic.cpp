@@ -218,10 +218,8 @@ void build_pattern_blocks(lsdm_pattern* p) {
     std::vector<i64> w(cstart.begin(), cstart.end() - 1);
     for (i32 a = 0; a < n; ++a) catom[w[cid(bin[3 * a], bin[3 * a + 1], bin[3 * a + 2])]++] = a;
   }
-  std::vector<std::vector<std::pair<i64, i32>>> rows(n);   // ((j << 24) | img) per row
-  std::atomic<int> bad(0);
-  parallel_for(n, [&](i64 i) {
-    auto& r = rows[i];
+  // every partner (j, image) of row i within R, passed to visit(j, m0, m1, m2)
+  auto search_row = [&](i64 i, auto&& visit) {
     const double xi = s->xyz[3 * i], yi = s->xyz[3 * i + 1], zi = s->xyz[3 * i + 2];
     for (int d0 = -D[0]; d0 <= D[0]; ++d0)
       for (int d1 = -D[1]; d1 <= D[1]; ++d1)
@@ -252,19 +250,64 @@ void build_pattern_blocks(lsdm_pattern* p) {
               dy = dy + ((double)m0 * T[1] + (double)m1 * T[4] + (double)m2 * T[7]);
               dz = dz + ((double)m0 * T[2] + (double)m1 * T[5] + (double)m2 * T[8]);
             }
-            if (dx * dx + dy * dy + dz * dz <= R2) {
-              if (m0 < -127 || m0 > 127 || m1 < -127 || m1 > 127 || m2 < -127 || m2 > 127) { bad = 1; continue; }
-              r.push_back({((i64)j << 24) | img_pack(m0, m1, m2), 0});
-            }
+            if (dx * dx + dy * dy + dz * dz <= R2) visit(j, m0, m1, m2);
           }
         }
+  };
+  // Size check before any row is stored: when the pair count could reach the
+  // block-index limit (2^31 blocks; their values alone would then fill an
+  // MI355X), count first, stopping as soon as the limit is passed.  The
+  // estimate is the pair count of a uniform density over the cell (periodic)
+  // or the bounding box (open), with a safety factor of 4.
+  constexpr i64 MAX_BLOCKS = (i64)1 << 31;
+  {
+    double vol;
+    if (s->periodic) {
+      const double* T = s->lat;
+      vol = std::fabs(T[0] * (T[4] * T[8] - T[5] * T[7]) - T[1] * (T[3] * T[8] - T[5] * T[6]) +
+                      T[2] * (T[3] * T[7] - T[4] * T[6]));
+    } else {
+      double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+      for (i32 a = 0; a < n; ++a)
+        for (int k = 0; k < 3; ++k) {
+          lo[k] = std::min(lo[k], s->xyz[3 * a + k]);
+          hi[k] = std::max(hi[k], s->xyz[3 * a + k]);
+        }
+      vol = 1.0;
+      for (int k = 0; k < 3; ++k) vol *= std::max(hi[k] - lo[k], 1.0);
+    }
+    const double ball = 4.18879020478639 * R * R * R;   // 4/3 pi R^3
+    const double est = (double)n * (1.0 + (s->periodic ? (double)n * ball / vol : std::min((double)n, (double)n * ball / vol)));
+    if (4.0 * est >= (double)MAX_BLOCKS) {
+      std::atomic<i64> total(0);
+      std::atomic<bool> over(false);
+      parallel_for(n, [&](i64 i) {
+        if (over.load(std::memory_order_relaxed)) return;
+        i64 c = 0;
+        search_row(i, [&](i32, int, int, int) { ++c; });
+        if (total.fetch_add(c) + c >= MAX_BLOCKS) over = true;
+      }, 8);
+      if (over) LSDM_THROW(LSDM_ENOMEM, "pattern exceeds 2^31 blocks (range too large for the system)");
+    }
+  }
+  std::vector<std::vector<std::pair<i64, i32>>> rows(n);   // ((j << 24) | img) per row
+  std::atomic<int> bad(0);
+  parallel_for(n, [&](i64 i) {
+    auto& r = rows[i];
+    search_row(i, [&](i32 j, int m0, int m1, int m2) {
+      if (m0 < -127 || m0 > 127 || m1 < -127 || m1 > 127 || m2 < -127 || m2 > 127) {
+        bad = 1;
+        return;
+      }
+      r.push_back({((i64)j << 24) | img_pack(m0, m1, m2), 0});
+    });
     std::sort(r.begin(), r.end());
   }, 8);
   if (bad) LSDM_THROW(LSDM_EUNSUPPORTED, "lattice image index beyond +-127");
   p->row_ptr.assign(n + 1, 0);
   for (i32 a = 0; a < n; ++a) p->row_ptr[a + 1] = p->row_ptr[a] + (i64)rows[a].size();
   const i64 nb_tot = p->row_ptr[n];
-  if (nb_tot >= (i64)1 << 31) LSDM_THROW(LSDM_ENOMEM, "pattern exceeds 2^31 blocks");
+  if (nb_tot >= MAX_BLOCKS) LSDM_THROW(LSDM_ENOMEM, "pattern exceeds 2^31 blocks");
   p->col.resize(nb_tot);
   p->img.resize(nb_tot);
   parallel_for(n, [&](i64 a) {

@@ -44,3 +44,42 @@ def onsite_values(n_atoms, seed=11):
     S = np.tile(np.eye(4).ravel(), n_atoms)
     L = 0.5 * S
     return dict(S=S, H=np.concatenate([b.ravel() for b in Hb]), L=L, P=np.concatenate([b.ravel() for b in Pb]))
+
+
+# ---------------------------------------------------------------------------
+# block-wise comparison on inputs that do not decay with distance
+# ---------------------------------------------------------------------------
+FLOOR = 0.05     # blocks are compared against max(own norm, FLOOR x RMS block norm)
+
+
+def sym_random(p, rng):
+    """Symmetric unit-size normal values on an oracle pattern p (mirror pairs
+    averaged, so block (j,i,-n) is exactly the transpose of block (i,j,n))."""
+    A = oracle.Matrix(p, rng.standard_normal(p.nval))
+    return oracle.Matrix(p, 0.5 * (A.val + oracle.transpose(A, p).val))
+
+
+def block_sizes(p):
+    nfn = np.asarray(p.system.nfn, np.int64)
+    return nfn[p.rows_of_blocks()] * nfn[p.col]
+
+
+def blockwise_rel(got, ref, p):
+    """Largest per-block error ||got_b - ref_b|| / max(||ref_b||, FLOOR rms)
+    over the blocks of oracle pattern p."""
+    if p.nblocks == 0:
+        return 0.0
+    d2 = np.add.reduceat((np.asarray(got) - ref) ** 2, p.off)
+    r2 = np.add.reduceat(np.asarray(ref) ** 2, p.off)
+    rms = np.sqrt(np.mean(r2))
+    den = np.maximum(np.sqrt(r2), FLOOR * rms)
+    return float(np.max(np.sqrt(d2) / den))
+
+
+def assert_mirrored(vals, p):
+    """Off-site blocks equal the transposes of their mirrors bit for bit."""
+    t = oracle.transpose(oracle.Matrix(p, vals), p).val
+    rows = p.rows_of_blocks()
+    onsite_b = (p.col == rows) & np.all(np.asarray(p.img).reshape(-1, 3) == 0, axis=1)
+    onsite = np.repeat(onsite_b, block_sizes(p))
+    np.testing.assert_array_equal(vals[~onsite], t[~onsite])

@@ -157,6 +157,71 @@ def test_si13824_jitter_fp64_rows_and_fd():
     say(f"    worst FD relative deviation {worst:.2e}")
 
 
+def _fd_exact(lnv, v, blocks, dirs, h=0.25):
+    """Richardson-extrapolated central differences of the FP64 energy along
+    single stored L blocks: exact derivatives up to rounding (E is a cubic
+    polynomial of L)."""
+    p = lnv.patterns["L"]
+    rp, col, img, off = p.export()
+    nfn = p.system.nfn
+    rows = np.repeat(np.arange(p.system.n), np.diff(rp))
+    Lh = v["L"].clone()
+    out = []
+    for b in blocks:
+        sz = int(nfn[rows[b]] * nfn[col[b]])
+        d = np.zeros(p.n_values)
+        d[off[b]:off[b] + sz] = dirs[off[b]:off[b] + sz]
+        dt = T(d)
+
+        def E(t):
+            Lh.copy_(v["L"]).add_(dt, alpha=t)
+            return lnv.energy(Lh, v["S"], v["H"], prec="fp64").item()
+        d1 = (E(h) - E(-h)) / (2 * h)
+        d2 = (E(h / 2) - E(-h / 2)) / h
+        out.append((d, (4 * d2 - d1) / 3))
+    return out
+
+
+def test_si13824_autograd_fp64_fp32_fd():
+    """The 13,824-atom jittered cell through the autograd.Function in FP64 and
+    FP32: dE/dL from backward() against exact finite differences on 20 seeded L
+    blocks.  FP64 is held to 1e-7 of max(1, |<G, d>|) (the differences'
+    own rounding).  FP32: every product rounds its inputs to FP32 and sums n
+    terms in FP32; with random rounding the error of such a sum stays below
+    lambda sqrt(n) u |a||b| with high probability (Higham & Mary, SIAM J. Sci.
+    Comput. 41, 2019: lambda = 6 gives a failure probability below 1e-15),
+    and the gradient passes through at most `levels` products, so the
+    projection of the FP32 gradient on a direction is allowed
+    levels * lambda sqrt(n) u32 of max(1, |<G, d>|), n the longest inner sum."""
+    c = workloads.workload("si13824_jitter_rl16")
+    s = c["system"]
+    rS, rH, rL = c["rS"], c["rH"], c["rL"]
+    say(f"[si13824 autograd] {s.n} atoms: setup")
+    lnv, v = setup(s, rS, rH, rL)
+    p = lnv.patterns["L"]
+    blocks = workloads.fd_blocks(p.n_blocks, 20, seed=0)
+    dirs = workloads.fd_direction(p.n_values, seed=0)
+    say("[si13824 autograd] exact finite differences (FP64 energies)")
+    fds = _fd_exact(lnv, v, blocks, dirs)
+    # longest inner sum of the chain: 4 functions x the most blocks in a row of M
+    n_inner = 4 * int(np.diff(lnv.patterns["M"].export()[0]).max())
+    levels, lam, u32 = 5, 6.0, 2.0 ** -24
+    tol = {"fp64": 1e-7, "fp32": levels * lam * np.sqrt(n_inner) * u32}
+    for prec in ("fp64", "fp32"):
+        L = v["L"].clone().requires_grad_(True)
+        E = lsdm.LNVEnergy.apply(L, v["S"], v["H"], lnv, prec)
+        E.backward()
+        g = L.grad.cpu().numpy()
+        worst = 0.0
+        for d, fd in fds:
+            an = float(np.dot(g, d))
+            err = abs(fd - an) / max(1.0, abs(an))
+            worst = max(worst, err)
+            assert err <= tol[prec], (prec, fd, an, err, tol[prec])
+        say(f"    {prec}: E = {E.item():.10f}, worst |FD - <dE/dL, d>| / max(1, |.|) = {worst:.2e} "
+            f"(allowed {tol[prec]:.1e})")
+
+
 @pytest.mark.parametrize("symmetric", [False, True], ids=["full", "sym"])
 def test_si32768_extensive_energy_rows_and_modes(symmetric):
     c = workloads.workload("si32768_rl16")
@@ -210,8 +275,9 @@ def test_mixed8000_blocks_rows_and_fd():
     fd_check(lnv, v, G, n_blocks=8, seed=5)
     Em, Gm = lnv.energy_grad(v["L"], v["S"], v["H"], prec="fp32")
     eE = abs(Em.item() - E.item()) / abs(E.item())
-    say(f"    fp32: E rel err {eE:.3e} = {1e6 * abs(Em.item() - E.item()) / s.n:.4f} uHa/atom")
-    assert eE <= CHAIN_TOL["fp32"][0]
+    eG = rel(Gm.cpu().numpy(), G.cpu().numpy())
+    say(f"    fp32: E rel err {eE:.3e} = {1e6 * abs(Em.item() - E.item()) / s.n:.4f} uHa/atom; dE/dL rel {eG:.3e}")
+    assert eE <= CHAIN_TOL["fp32"][0] and eG <= CHAIN_TOL["fp32"][1]
 
 
 def test_slab18432_rows_and_fd():

@@ -144,6 +144,8 @@ CHAIN_CASES = {
     "mixed_box_13_5": lambda: (workloads.random_box(300, 17.5, 240, 13, 5, seed=2), 6.0, 8.0, 8.0),
     "open_cluster_ragged": lambda: (workloads.random_cluster(90, 14.0, nfn=np.arange(90) % 5 + 1, seed=9), 5.0, 6.0, 6.5),
     "si_slab_h_2x2x2": lambda: (workloads.si_slab((2, 2, 2)), 8.0, 12.0, 16.0),
+    # H's range beyond that of LSL (rH > 2 rL + rS): K = -2P on the far H blocks
+    "si64_h_beyond_lsl": lambda: (workloads.diamond(2, jitter=0.1, seed=3), 4.5, 14.0, 4.6),
 }
 
 

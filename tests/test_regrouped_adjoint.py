@@ -27,6 +27,8 @@ CASES = {
     "open_cluster_ragged": lambda: (workloads.random_cluster(60, 12.0, nfn=np.arange(60) % 5 + 1, seed=9),
                                     5.0, 6.0, 6.5),
     "mixed_box_13_5": lambda: (workloads.random_box(120, 14.0, 96, 13, 5, seed=3), 6.0, 8.0, 8.0),
+    # H's range beyond the range of LSL (rH > 2 rL + rS)
+    "si64_h_beyond_lsl": lambda: (workloads.diamond(2, jitter=0.1, seed=3), 4.5, 14.0, 4.6),
 }
 
 
@@ -62,8 +64,11 @@ def test_symmetric_adjoint_grouping_equals_gradient(name):
     Gref = oracle.lnv_gradient(L, S, H, rS, rH, rL)
     assert _rel(B3 + V + VT, Gref.val) <= 1e-13, _rel(B3 + V + VT, Gref.val)
     # the grouping is not an identity of arbitrary matrices: dropping the
-    # transposed half of V breaks it
-    assert _rel(B3 + 2.0 * V, Gref.val) > 1e-3
+    # transposed half of V breaks it (with L's range below the second-neighbour
+    # distance V is nearly symmetric here, so that case is left to the
+    # non-decaying test below)
+    if name != "si64_h_beyond_lsl":
+        assert _rel(B3 + 2.0 * V, Gref.val) > 1e-3
 
 
 def _sym_random(p, rng):
@@ -71,7 +76,7 @@ def _sym_random(p, rng):
     return oracle.Matrix(p, 0.5 * (A.val + oracle.transpose(A, p).val))
 
 
-@pytest.mark.parametrize("name", ["si64_jitter_rl16", "open_cluster_ragged"])
+@pytest.mark.parametrize("name", ["si64_jitter_rl16", "open_cluster_ragged", "si64_h_beyond_lsl"])
 def test_symmetric_adjoint_ranges_without_decay(name):
     """Symmetric values of unit size at every range (no decay with distance),
     so that an element dropped by a short range shows: the chain's ranges give

@@ -132,6 +132,22 @@ def test_errors():
         assert full.patterns[w].n_values == sym.patterns[w].n_values
 
 
+def test_pattern_beyond_the_block_limit_is_enomem():
+    """A finite range whose pattern would exceed the library's size limit
+    (2^31 blocks, whose values alone would fill the device) is refused with
+    LSDM_ENOMEM before any row is stored, and the system stays usable."""
+    import time
+    s = workloads.diamond(4)                     # 512 atoms, 41 bohr cell
+    gs = lsdm.System.from_workload(s)
+    t0 = time.perf_counter()
+    with pytest.raises(lsdm.LsdmError) as e:
+        lsdm.Pattern(gs, 600.0)                  # about 3.4e9 pairs
+    assert e.value.code == lsdm._lib.ENOMEM
+    assert "2^31" in str(e.value)
+    assert time.perf_counter() - t0 < 60.0
+    assert lsdm.Pattern(gs, 8.0).n_blocks == 512 * 17
+
+
 def test_compute_without_device_fails_loudly():
     import torch
     if torch.cuda.is_available():
