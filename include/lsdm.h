@@ -153,6 +153,16 @@ int lsdm_multiply_adjoint(const lsdm_plan* plan, int prec, const double* dCbar, 
  * pattern; Tr(AB) for symmetric B).  FP64 with per-thread compensated sums and
  * a fixed-order tree, so the result is bitwise reproducible.  dOut: device. */
 int lsdm_dot(const lsdm_pattern* p, const double* dA, const double* dB, double* dOut, void* stream);
+/* lsdm_dot without allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments and the same result bit for bit; it allocates
+ * nothing and does not synchronise (the result is ready when the stream
+ * reaches it).  Its partial sums live in a static device array of the library
+ * (16 KiB per device, held until the process ends; any pattern fits it, the
+ * grid is fixed).  That array is shared by every call on a device: calls that
+ * overlap on one device, on one stream or several, race.
+ * Errors: LSDM_EINVAL (null argument), LSDM_EDEVICE. */
+int lsdm_dot_noalloc(const lsdm_pattern* p, const double* dA, const double* dB, double* dOut, void* stream);
 
 /* ---- the LNV chain ------------------------------------------------------- */
 /* Patterns of S (range rS), H (rH) and L (rL) plus the intermediates

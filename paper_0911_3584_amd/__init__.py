@@ -149,13 +149,17 @@ def multiply_adjoint(plan, Cbar, A, B, Abar=None, Bbar=None, prec="fp64", stream
     return Abar, Bbar
 
 
-def dot(pattern, A, B, out=None, stream=None):
-    """sum over pattern blocks of <A_b, B_b> as a one-element device tensor."""
+def dot(pattern, A, B, out=None, stream=None, noalloc=False):
+    """sum over pattern blocks of <A_b, B_b> as a one-element device tensor.
+    noalloc=True: the variant that allocates nothing and does not synchronise
+    (its partial sums sit in the library's static scratch; concurrent calls
+    on one device race), for graph capture and serving loops."""
     import torch
     if out is None:
         out = torch.empty(1, dtype=torch.float64, device=A.device)
-    check(lib().lsdm_dot(pattern._h, _dev(A, pattern.n_values, "A"), _dev(B, pattern.n_values, "B"),
-                         _dev(out, 1, "out"), _stream(stream)))
+    fn = lib().lsdm_dot_noalloc if noalloc else lib().lsdm_dot
+    check(fn(pattern._h, _dev(A, pattern.n_values, "A"), _dev(B, pattern.n_values, "B"),
+             _dev(out, 1, "out"), _stream(stream)))
     return out
 
 

@@ -28,6 +28,7 @@ SIGNATURES = {
     "lsdm_multiply": (_I, [_P, _I, _D, _P, _P, _D, _P, _P]),
     "lsdm_multiply_adjoint": (_I, [_P, _I, _P, _P, _P, _P, _P, _P]),
     "lsdm_dot": (_I, [_P, _P, _P, _P, _P]),
+    "lsdm_dot_noalloc": (_I, [_P, _P, _P, _P, _P]),
     "lsdm_lnv_create": (_I, [_P, _D, _D, _D, _PP]),
     "lsdm_lnv_create_ex": (_I, [_P, _D, _D, _D, _I, _PP]),
     "lsdm_lnv_pattern": (_I, [_P, _I, _PP]),

@@ -776,6 +776,19 @@ int lsdm_dot(const lsdm_pattern* p, const double* dA, const double* dB, double* 
   });
 }
 
+int lsdm_dot_noalloc(const lsdm_pattern* p, const double* dA, const double* dB, double* dOut, void* stream) {
+  return guarded([&] {
+    require_device();
+    if (!p || !dA || !dB || !dOut) LSDM_THROW(LSDM_EINVAL, "null argument");
+    // the fixed grid needs DOT_SCRATCH partials whatever the pattern's size,
+    // so every pattern fits the scratch
+    static_assert(2 * DOT_BLOCKS <= DOT_SCRATCH, "dot partials exceed the scratch");
+    double* part = dot_scratch();
+    dot(dA, dB, p->nval, 1.0, part, dOut, (hipStream_t)stream);
+    check_launch();
+  });
+}
+
 int lsdm_lnv_create(const lsdm_system* sys, double rS, double rH, double rL, lsdm_lnv** out) {
   return lsdm_lnv_create_ex(sys, rS, rH, rL, 0, out);
 }

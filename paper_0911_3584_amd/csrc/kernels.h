@@ -6,6 +6,10 @@
 namespace lsdm {
 
 constexpr int DOT_BLOCKS = 1024;   // fixed grid of the reproducible dot
+constexpr int DOT_SCRATCH = 2 * DOT_BLOCKS;   // partial sums of one dot (doubles)
+// device address, on the current device, of the dot's static scratch (looked
+// up on the first call per device)
+double* dot_scratch();
 
 // layout maps of a pattern (built on first use; symbolic.cpp)
 void ensure_maps(lsdm_pattern* p);

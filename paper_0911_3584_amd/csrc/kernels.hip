@@ -1418,4 +1418,29 @@ void dot(const double* a, const double* b, i64 n, double scale, double* partial,
   hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, st, partial, DOT_BLOCKS, scale, out);
 }
 
+// Scratch of the dot that allocates nothing (lsdm_dot_noalloc): the partial
+// sums of the fixed grid, DOT_SCRATCH doubles (16 KiB), one copy per device,
+// held until the process ends.  Every partial is written before it is read,
+// so nothing needs clearing between calls; calls that overlap on one device
+// share it and race.
+static __device__ __align__(256) double scratch[DOT_SCRATCH];
+
+double* dot_scratch() {
+  static std::mutex mu;
+  static std::map<int, double*> addr;   // device -> device address of `scratch`
+  int d = 0;
+  HIP_CHECK(hipGetDevice(&d));
+  std::lock_guard<std::mutex> g(mu);
+  auto it = addr.find(d);
+  if (it != addr.end()) return it->second;
+  // the array's name is a host-side stand-in; its address on device d comes
+  // from the runtime, looked up once with d current
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    LSDM_THROW(LSDM_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  addr.emplace(d, static_cast<double*>(ptr));
+  return static_cast<double*>(ptr);
+}
+
 }  // namespace lsdm
