@@ -36,6 +36,7 @@
 namespace lsdm {
 void build_system(lsdm_system* s);
 void build_pattern_blocks(lsdm_pattern* p);
+void build_pattern_reach(lsdm_pattern* p, const lsdm_pattern* A, const lsdm_pattern* B);
 void build_strips(lsdm_pattern* p);
 void build_plan(lsdm_plan* pl);
 
@@ -109,6 +110,17 @@ static lsdm_pattern* make_pattern(const lsdm_system* sys, double R) {
   p->sys = sys;
   p->R = R;
   build_pattern_blocks(p.get());
+  build_strips(p.get());
+  return p.release();
+}
+
+// the blocks of the sphere of R that a product of A's and B's patterns reaches
+static lsdm_pattern* make_reach_pattern(const lsdm_system* sys, double R, const lsdm_pattern* A,
+                                        const lsdm_pattern* B) {
+  std::unique_ptr<lsdm_pattern> p(new lsdm_pattern());
+  p->sys = sys;
+  p->R = R;
+  build_pattern_reach(p.get(), A, B);
   build_strips(p.get());
   return p.release();
 }
@@ -255,7 +267,10 @@ static void lnv_build(lsdm_lnv* L) {
   L->pS = make_pattern(L->sys, rS);
   L->pH = make_pattern(L->sys, rH);
   L->pL = make_pattern(L->sys, rL);
-  L->pX = make_pattern(L->sys, rX);
+  // X = LS is zero outside the blocks L S (or S L) reaches: on a crystal a
+  // fifth of the rL + rS sphere (pairs no lattice path of an L step and an S
+  // step connects), which every product that reads or writes X then skips
+  L->pX = make_reach_pattern(L->sys, rX, L->pL, L->pS);
   L->pM = make_pattern(L->sys, rM);
   L->F1 = make_plan(L->pL, 0, L->pS, 0, L->pX);
   // symmetric mode: M = LSL, P = LSLSL and XᵀHX are symmetric, so their

@@ -995,7 +995,8 @@ __global__ void k_rc_onsite(PatDev A, PatDev B, const i32* __restrict__ patom, c
 }
 
 // C = alpha (RR + D_A B + A D_B - D_A D_B) + beta C in FP64, one thread per
-// output element (16 per block), the blocks it needs read from the maps
+// output element (16 per block), the blocks it needs read from the maps; a
+// half-output plan (half = 1) skips the strips its mirror fill writes
 template <bool TA>
 __global__ void k_rc_apply(const uint8_t* __restrict__ cmask, const i32* __restrict__ srow,
                            const i32* __restrict__ csquad, const i32* __restrict__ csimg,
@@ -1003,9 +1004,10 @@ __global__ void k_rc_apply(const uint8_t* __restrict__ cmask, const i32* __restr
                            const i32* __restrict__ amap, const i32* __restrict__ aon, const i32* __restrict__ bon,
                            const double* __restrict__ A64, const double* __restrict__ B64,
                            const float* __restrict__ RR, double* __restrict__ C64, i64 ncstrips, double alpha,
-                           double beta) {
+                           double beta, int half) {
   for (i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x; g < ncstrips * 64; g += (i64)gridDim.x * blockDim.x) {
     const i64 st = g >> 6, blk = g >> 4;
+    if (half && !keep_strip(srow[st], csquad[st], csimg[st])) continue;
     const int t = (int)((g >> 4) & 3), e = (int)(g & 15), r = e >> 2, c = e & 3;
     const bool in = (cmask[st] >> t) & 1;
     double acc = 0.0;
@@ -1328,12 +1330,12 @@ void rc_correct(const lsdm_plan* cpl, const double* A64, const double* B64, cons
     hipLaunchKernelGGL((k_rc_apply<true>), g, b, 0, st, C->d_smask.as<uint8_t>(), C->d_srow.as<i32>(),
                        C->d_squad.as<i32>(), C->d_simg.as<i32>(), s->d_patom.as<i32>(), pl->rc_np,
                        pl->d_rc_b.as<i32>(), pl->d_rc_a.as<i32>(), pl->d_rc_aon.as<i32>(), pl->d_rc_bon.as<i32>(), A64,
-                       B64, RR, C64, C->n_strips, alpha, beta);
+                       B64, RR, C64, C->n_strips, alpha, beta, pl->half);
   else
     hipLaunchKernelGGL((k_rc_apply<false>), g, b, 0, st, C->d_smask.as<uint8_t>(), C->d_srow.as<i32>(),
                        C->d_squad.as<i32>(), C->d_simg.as<i32>(), s->d_patom.as<i32>(), pl->rc_np,
                        pl->d_rc_b.as<i32>(), pl->d_rc_a.as<i32>(), pl->d_rc_aon.as<i32>(), pl->d_rc_bon.as<i32>(), A64,
-                       B64, RR, C64, C->n_strips, alpha, beta);
+                       B64, RR, C64, C->n_strips, alpha, beta, pl->half);
 }
 
 void to_bf16(const float* in, unsigned short* outR, unsigned short* outC, i64 n, hipStream_t st) {

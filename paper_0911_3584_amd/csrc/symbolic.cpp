@@ -321,6 +321,52 @@ void build_pattern_blocks(lsdm_pattern* p) {
 }
 
 // ---------------------------------------------------------------------------
+// Structural pattern of a product: the blocks (i, k, n) of the sphere of
+// p->R reachable as (A B)_{i,(k,n)} = sum over (l, m) of A_{i,(l,m)}
+// B_{l,(k,n-m)}, or the same with A and B exchanged.  A product of matrices
+// on these patterns is exactly zero on the other blocks of the sphere (no
+// term reaches them), so they need no storage and no work; taking both orders
+// keeps the pattern symmetric when A's and B's are (then the second set is the
+// transpose of the first), which transposed uses of the product need.
+// ---------------------------------------------------------------------------
+void build_pattern_reach(lsdm_pattern* p, const lsdm_pattern* A, const lsdm_pattern* B) {
+  build_pattern_blocks(p);   // the sphere
+  const i32 n = p->sys->n_atoms;
+  std::vector<std::vector<std::pair<i32, i32>>> rows(n);   // (col, img) kept per row
+  parallel_for(n, [&](i64 i) {
+    std::vector<i64> reach;
+    for (int pass = 0; pass < 2; ++pass) {
+      const lsdm_pattern* X = pass ? B : A;
+      const lsdm_pattern* Y = pass ? A : B;
+      for (i64 b = X->row_ptr[i]; b < X->row_ptr[i + 1]; ++b) {
+        const i32 l = X->col[b], m = X->img[b];
+        for (i64 c = Y->row_ptr[l]; c < Y->row_ptr[l + 1]; ++c)
+          reach.push_back(((i64)Y->col[c] << 24) | img_add(m, Y->img[c]));
+      }
+    }
+    std::sort(reach.begin(), reach.end());
+    reach.erase(std::unique(reach.begin(), reach.end()), reach.end());
+    auto& r = rows[i];
+    for (i64 b = p->row_ptr[i]; b < p->row_ptr[i + 1]; ++b)
+      if (std::binary_search(reach.begin(), reach.end(), ((i64)p->col[b] << 24) | p->img[b]))
+        r.push_back({p->col[b], p->img[b]});
+  }, 8);
+  std::vector<i64> rp(n + 1, 0);
+  for (i32 a = 0; a < n; ++a) rp[a + 1] = rp[a] + (i64)rows[a].size();
+  p->row_ptr = rp;
+  p->col.assign(rp[n], 0);
+  p->img.assign(rp[n], 0);
+  parallel_for(n, [&](i64 a) {
+    i64 w = rp[a];
+    for (auto& e : rows[a]) {
+      p->col[w] = e.first;
+      p->img[w] = e.second;
+      ++w;
+    }
+  });
+}
+
+// ---------------------------------------------------------------------------
 // strip layout of a pattern whose block layout (row_ptr, col, img) is filled
 // ---------------------------------------------------------------------------
 static i64 find_strip(const lsdm_pattern* p, i32 row, i64 key) {

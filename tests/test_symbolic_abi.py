@@ -77,21 +77,100 @@ def test_plan_triples_equal_oracle(name, tA, tB):
     assert plan.flops == fl
 
 
+def _reach_pattern(s, rL, rS):
+    """X's structural pattern through the oracle: the blocks of the rL + rS
+    sphere where the product of all-ones L and S (or S and L) is nonzero."""
+    pS, pL, pX = oracle.pattern(s, rS), oracle.pattern(s, rL), oracle.pattern(s, rL + rS)
+    one = lambda p: oracle.Matrix(p, np.ones(p.nval))
+    nz = (oracle.multiply(one(pL), one(pS), pX).val != 0) | (oracle.multiply(one(pS), one(pL), pX).val != 0)
+    keep = np.add.reduceat(nz.astype(np.int64), pX.off) > 0
+    rows = pX.rows_of_blocks()[keep]
+    row_ptr = np.zeros(s.n + 1, np.int64)
+    np.cumsum(np.bincount(rows, minlength=s.n), out=row_ptr[1:])
+    nfn = np.asarray(s.nfn, np.int64)
+    sz = nfn[rows] * nfn[pX.col[keep]]
+    off = np.zeros(sz.size, np.int64)
+    off[1:] = np.cumsum(sz)[:-1]
+    sub = oracle.Pattern(s, pX.R, row_ptr, pX.col[keep].copy(), pX.img[keep].copy(), off, int(sz.sum()),
+                         np.ones(s.n, np.uint8))
+    return sub, pX, keep
+
+
+def _diamond_reach_count(rL, rS, a=10.26):
+    """Sites k within rL + rS of a site where some site l has |l| <= rL and
+    |k - l| <= rS, or |l| <= rS and |k - l| <= rL (integer a/4 coordinates)."""
+    m = int(np.ceil(4 * (rL + rS) / a)) + 2
+    g = np.arange(-m, m + 1)
+    x, y, z = (v.ravel() for v in np.meshgrid(g, g, g, indexing="ij"))
+    sm = x + y + z
+    even = (x % 2 == 0) & (y % 2 == 0) & (z % 2 == 0) & (sm % 4 == 0)
+    odd = (x % 2 != 0) & (y % 2 != 0) & (z % 2 != 0) & (sm % 4 == 3)
+    pts = np.stack([x, y, z], 1)[even | odd]
+    u2 = (a / 4.0) ** 2
+    r2 = (pts ** 2).sum(1) * u2
+    K = pts[r2 <= (rL + rS) ** 2]
+    hit = np.zeros(len(K), bool)
+    for r1, r2_ in ((rL, rS), (rS, rL)):
+        Lp = pts[r2 <= r1 * r1]
+        d = ((K[:, None, :] - Lp[None, :, :]) ** 2).sum(2) * u2
+        hit |= np.any(d <= r2_ * r2_, axis=1)
+    return int(hit.sum()), int(len(K))
+
+
+def test_structural_x_pattern():
+    """X = LS on the blocks of the rL + rS sphere that L S or S L reaches: the
+    library's pattern equals the oracle's reach set (all-ones products), its
+    rows hold the integer-enumerated count on perfect diamond, the dropped
+    blocks of the oracle's X on seeded values are exactly zero, and the
+    pattern is symmetric."""
+    for s, rS, rH, rL, perfect in ((workloads.diamond(2), 8.0, 12.0, 16.0, True),
+                                   (workloads.diamond(2), 8.0, 12.0, 12.0, True),
+                                   (workloads.diamond(2, jitter=0.1, seed=7), 8.0, 12.0, 16.0, False),
+                                   (workloads.random_cluster(60, 12.0, nfn=np.arange(60) % 5 + 1, seed=9), 5.0, 6.0, 6.5,
+                                    False)):
+        lnv = lsdm.LNV(lsdm.System.from_workload(s), rS, rH, rL)
+        sub, sphere, keep = _reach_pattern(s, rL, rS)
+        assert same_pattern(lnv.patterns["X"], sub)
+        if perfect:
+            reach, ball = _diamond_reach_count(rL, rS)
+            assert np.all(np.diff(sub.row_ptr) == reach) and reach < ball
+        inp = oracle.make_inputs(s, rS, rH, rL)
+        X = oracle.multiply(inp["L"], inp["S"], sphere)
+        dropped = np.repeat(~keep, np.diff(np.append(sphere.off, sphere.nval)))
+        assert np.all(X.val[dropped] == 0.0)
+        assert np.count_nonzero(X.val[~dropped]) > 0
+        T = oracle.transpose(oracle.Matrix(sub, np.arange(sub.nval, dtype=np.float64) + 1.0), sub)
+        assert np.all(T.val != 0.0)        # every mirror block is in the pattern
+
+
 def test_lnv_work_counts_si64():
-    """Useful triples per atom of the chain on perfect diamond Si, RL = 12:
-    forward X, LSL, LSLSL and the five adjoint products."""
+    """Useful triples of the chain on perfect diamond Si, RL = 12: forward X,
+    LSL, LSLSL and the five adjoint products, against the oracle's own counts
+    on the same patterns (X on its structural pattern)."""
     s = workloads.diamond(2)
-    lnv = lsdm.LNV(lsdm.System.from_workload(s), 8.0, 12.0, 12.0)
+    rS, rH, rL = 8.0, 12.0, 12.0
+    lnv = lsdm.LNV(lsdm.System.from_workload(s), rS, rH, rL)
     nf, ff = lnv.info(False)
     ng, fg = lnv.info(True)
-    from tests.test_oracle_pins import diamond_triples
-    R = oracle.chain_ranges(8.0, 12.0, 12.0)
-    fwd = diamond_triples(12, 8, R["X"]) + diamond_triples(R["X"], 12, R["M"]) + diamond_triples(R["X"], R["M"], 12)
-    assert nf == s.n * fwd
+    R = oracle.chain_ranges(rS, rH, rL)
+    pS, pH, pL, pM = (oracle.pattern(s, R[w]) for w in "SHLM")
+    pX = _reach_pattern(s, rL, rS)[0]
+    one = lambda p: oracle.Matrix(p, np.ones(p.nval))
+    T = lambda p: oracle.transpose(one(p), p)
+
+    def cnt(A, B, pC):
+        return oracle.multiply(A, B, pC, count=True)[1]
+    fwd = cnt(one(pL), one(pS), pX) + cnt(one(pX), one(pL), pM) + cnt(one(pX), one(pM), pH)
+    assert nf == fwd
     assert ff == 128.0 * nf
-    adj = (diamond_triples(R["X"], 12, R["M"]) + diamond_triples(12, R["M"], R["X"]) + diamond_triples(R["M"], 12, R["X"])
-           + diamond_triples(R["X"], R["M"], 12) + diamond_triples(R["X"], 8, 12))
-    assert ng == s.n * (fwd + adj)
+    adj = (cnt(T(pX), one(pH), pM) + cnt(one(pH), one(pM), pX) + cnt(one(pM), one(pL), pX)
+           + cnt(T(pX), one(pM), pL) + cnt(one(pX), one(pS), pL))
+    assert ng == fwd + adj
+    # on the sphere X the chain would do more: the structural pattern saves work
+    from tests.test_oracle_pins import diamond_triples
+    full_fwd = s.n * (diamond_triples(12, 8, R["X"]) + diamond_triples(R["X"], 12, R["M"])
+                      + diamond_triples(R["X"], R["M"], 12))
+    assert nf < full_fwd
 
 
 def test_errors():
