@@ -126,8 +126,8 @@ def cpu_baseline(cfg, flops_per_atom):
 # the symbolic pass (atom order, tiles, steps) and the chain's choice of plans
 KERNEL_SRC = [os.path.join(ROOT, "paper_0911_3584_amd", "csrc", f)
               for f in ("kernels.hip", "symbolic.cpp", "plan_common.h", "lsdm_internal.h", "api.cpp")]
-PRODUCT_KERNEL = {"fp64": "k_gprod<double>", "fp32": "k_gprod_rs<float>", "bf16": "k_gprod_bf16",
-                  "fp32_rc": "k_gprod_rs<float> (R_A R_B; FP64 corrections in k_rc_apply not counted)"}
+PRODUCT_KERNEL = {"fp64": "k_gprod<double>", "fp32": "k_gprod<float>", "bf16": "k_gprod_bf16",
+                  "fp32_rc": "k_gprod<float> (R_A R_B; FP64 corrections in k_rc_apply not counted)"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_si32768.json")
 
 

@@ -397,17 +397,24 @@ static void lnv_backward(lsdm_lnv* L, double* dG, hipStream_t st) {
 // in FP64.  Intermediates are rounded to bf16 once, when they become operands.
 enum { LR, LC, SC, HR, HC, XR, XC, MC, MbR, MbC, XbR };
 
-static void bf16_workspaces(lsdm_lnv* L) {
+// The copies are zeroed once when allocated: later writes touch only the
+// pattern's elements (inputs) or whole strips (products, mirror fills), so
+// padding and absent blocks stay zero.
+static void bf16_workspaces(lsdm_lnv* L, hipStream_t st) {
   if (L->b16_ready) return;
   const lsdm_pattern* who[11] = {L->pL, L->pL, L->pS, L->pH, L->pH, L->pX, L->pX, L->pM, L->pM, L->pM, L->pX};
-  for (int k = 0; k < 11; ++k) L->b16[k].alloc(strip_bytes(who[k], 2));
+  for (int k = 0; k < 11; ++k) {
+    L->b16[k].alloc(strip_bytes(who[k], 2));
+    fill<unsigned short>(L->b16[k].as<unsigned short>(), (i64)(L->b16[k].bytes / 2), 0, st);
+  }
   L->b16_ready = true;
 }
 
 static void chain_product_bf16(lsdm_lnv* L, int w, const unsigned short* A, const unsigned short* B, float* C,
-                               double alpha, double beta, hipStream_t st) {
+                               double alpha, double beta, hipStream_t st, unsigned short* outR = nullptr,
+                               unsigned short* outC = nullptr) {
   if (!L->prof) {
-    product_bf16(chain_plan(L, w), A, B, C, alpha, beta, st);
+    product_bf16(chain_plan(L, w), A, B, C, alpha, beta, st, outR, outC);
     return;
   }
   while (L->ev_pool.size() < L->ev_used + 2) {
@@ -416,7 +423,7 @@ static void chain_product_bf16(lsdm_lnv* L, int w, const unsigned short* A, cons
     L->ev_pool.push_back(e);
   }
   HIP_CHECK(hipEventRecord(L->ev_pool[L->ev_used], st));
-  product_bf16(chain_plan(L, w), A, B, C, alpha, beta, st);
+  product_bf16(chain_plan(L, w), A, B, C, alpha, beta, st, outR, outC);
   HIP_CHECK(hipEventRecord(L->ev_pool[L->ev_used + 1], st));
   L->ev_used += 2;
   L->ev_prod.push_back(w);
@@ -425,32 +432,31 @@ static void chain_product_bf16(lsdm_lnv* L, int w, const unsigned short* A, cons
 static void lnv_forward_bf16(lsdm_lnv* L, const double* dL, const double* dS, const double* dH, double* dK,
                              double* dE, hipStream_t st) {
   typedef unsigned short u16;
-  bf16_workspaces(L);
+  bf16_workspaces(L, st);
   auto h = [&](int k) { return L->b16[k].as<u16>(); };
-  float* wL = L->wL.as<float>();
-  float* wS = L->wS.as<float>();
-  float* wH = L->wH.as<float>();
-  float* wX = L->wX.as<float>();
   float* wM = L->wM.as<float>();
   float* wP = L->wP.as<float>();
   double* wH64 = L->wH64.as<double>();
   double* wK = L->wK.as<double>();
-  fill<float>(wL, L->pL->n_strips * 64, 0.f, st);
-  fill<float>(wS, L->pS->n_strips * 64, 0.f, st);
-  fill<float>(wH, L->pH->n_strips * 64, 0.f, st);
   fill<double>(wH64, L->pH->n_strips * 64, 0.0, st);
-  user_to_strip<float>(L->pL, dL, wL, 1.0, st);
-  user_to_strip<float>(L->pS, dS, wS, 1.0, st);
-  user_to_strip<float>(L->pH, dH, wH, 1.0, st);
   user_to_strip<double>(L->pH, dH, wH64, 1.0, st);
-  to_bf16(wL, h(LR), h(LC), L->pL->n_strips * 64, st);
-  to_bf16(wS, nullptr, h(SC), L->pS->n_strips * 64, st);
-  to_bf16(wH, h(HR), h(HC), L->pH->n_strips * 64, st);
-  chain_product_bf16(L, 0, h(LR), h(SC), wX, 1.0, 0.0, st);    // X = LS
-  to_bf16(wX, h(XR), h(XC), L->pX->n_strips * 64, st);
-  chain_product_bf16(L, 1, h(XR), h(LC), wM, 1.0, 0.0, st);    // M = XL
-  if (L->sym) sym_fill<float>(L->pM, wM, st);
-  to_bf16(wM, nullptr, h(MC), L->pM->n_strips * 64, st);
+  // inputs straight from the caller's layout to their bf16 copies
+  user_to_bf16(L->pL, dL, h(LR), h(LC), st);
+  user_to_bf16(L->pS, dS, nullptr, h(SC), st);
+  user_to_bf16(L->pH, dH, h(HR), h(HC), st);
+  if (!L->sym) {                                               // FP32 H for Mbar += 6H
+    float* wH = L->wH.as<float>();
+    fill<float>(wH, L->pH->n_strips * 64, 0.f, st);
+    user_to_strip<float>(L->pH, dH, wH, 1.0, st);
+  }
+  // X = LS: only its bf16 copies are used later
+  chain_product_bf16(L, 0, h(LR), h(SC), nullptr, 1.0, 0.0, st, h(XR), h(XC));
+  // M = XL: FP32 for K, block-transposed bf16 copy for the products
+  chain_product_bf16(L, 1, h(XR), h(LC), wM, 1.0, 0.0, st, nullptr, h(MC));
+  if (L->sym) {
+    sym_fill<float>(L->pM, wM, st);
+    sym_fill<u16>(L->pM, h(MC), st);                           // the mirror rule holds for transposed blocks too
+  }
   chain_product_bf16(L, 2, h(XR), h(MC), wP, 1.0, 0.0, st);    // P = XM on H's range
   if (L->sym) sym_fill<float>(L->pH, wP, st);
   kassembly<float>(L, wM, wP, wK, st);
@@ -466,18 +472,20 @@ static void lnv_backward_bf16(lsdm_lnv* L, double* dG, hipStream_t st) {
   float* wMb = L->wMb.as<float>();
   float* wXb = L->wXb.as<float>();
   float* wLb = L->wLb.as<float>();
-  chain_product_bf16(L, 3, h(XC), h(HC), wMb, -4.0, 0.0, st);   // Mbar = X^T Pbar
-  if (!L->sym) scatter_h<float>(L, wH, wMb, 6.0, st);             // Mbar += 6H
-  to_bf16(wMb, h(MbR), L->sym ? nullptr : h(MbC), L->pM->n_strips * 64, st);
-  chain_product_bf16(L, 4, h(HR), h(MC), wXb, -4.0, 0.0, st);   // Xbar = Pbar M
   if (!L->sym) {
-    chain_product_bf16(L, 5, h(MbR), h(LC), wXb, 1.0, 1.0, st); // Xbar += Mbar L
+    chain_product_bf16(L, 3, h(XC), h(HC), wMb, -4.0, 0.0, st);   // Mbar = X^T Pbar
+    scatter_h<float>(L, wH, wMb, 6.0, st);                          // Mbar += 6H
+    to_bf16(wMb, h(MbR), h(MbC), L->pM->n_strips * 64, st);
+    chain_product_bf16(L, 4, h(HR), h(MC), wXb, -4.0, 0.0, st);   // Xbar = Pbar M
+    chain_product_bf16(L, 5, h(MbR), h(LC), wXb, 1.0, 1.0, st);   // Xbar += Mbar L
     to_bf16(wXb, h(XbR), nullptr, L->pX->n_strips * 64, st);
-    chain_product_bf16(L, 6, h(XC), h(MbC), wLb, 1.0, 0.0, st); // Lbar = X^T Mbar
-    chain_product_bf16(L, 7, h(XbR), h(SC), wLb, 1.0, 1.0, st); // Lbar += Xbar S
+    chain_product_bf16(L, 6, h(XC), h(MbC), wLb, 1.0, 0.0, st);   // Lbar = X^T Mbar
+    chain_product_bf16(L, 7, h(XbR), h(SC), wLb, 1.0, 1.0, st);   // Lbar += Xbar S
   } else {
     float* wV = L->wV.as<float>();
-    to_bf16(wXb, h(XbR), nullptr, L->pX->n_strips * 64, st);
+    // Mbar and Xbar are operands only: their bf16 copies come from the epilogues
+    chain_product_bf16(L, 3, h(XC), h(HC), nullptr, -4.0, 0.0, st, h(MbR), nullptr);   // Mbar = X^T Pbar
+    chain_product_bf16(L, 4, h(HR), h(MC), nullptr, -4.0, 0.0, st, h(XbR), nullptr);   // Xbar = Pbar M
     chain_product_bf16(L, 5, h(MbR), h(XC), wLb, 1.0, 0.0, st); // Lbar = Mbar X (half)
     chain_product_bf16(L, 6, h(HR), h(XC), wV, 6.0, 0.0, st);   // V = 6 H X
     chain_product_bf16(L, 7, h(XbR), h(SC), wV, 1.0, 1.0, st);  // V += Xbar S

@@ -37,9 +37,14 @@ void rc_correct(const lsdm_plan* pl, const double* A64, const double* B64, const
                 double beta, hipStream_t st);
 // BF16 path: fp32 strips -> bf16 copies (row-major R and/or block-transposed C)
 void to_bf16(const float* in, unsigned short* outR, unsigned short* outC, i64 n, hipStream_t st);
-// C (fp32) = alpha P_C(op(A) B) + beta C with bf16 operands (A: R copy, or C copy of X when transposed; B: C copy)
+// caller's block layout (FP64) -> bf16 strip copies (R and/or C, either null)
+void user_to_bf16(const lsdm_pattern* p, const double* user, unsigned short* outR, unsigned short* outC,
+                  hipStream_t st);
+// C (fp32) = alpha P_C(op(A) B) + beta C with bf16 operands (A: R copy, or C copy of X when transposed; B: C copy);
+// C may be null when only the bf16 copies of the result are wanted (outR, outC: nullable, written from the
+// FP32 result in the product's epilogue)
 void product_bf16(const lsdm_plan* pl, const unsigned short* A, const unsigned short* B, float* C, double alpha,
-                  double beta, hipStream_t st);
+                  double beta, hipStream_t st, unsigned short* outR = nullptr, unsigned short* outC = nullptr);
 template <class T> void kassembly(const lsdm_lnv* L, const T* M, const T* P, double* K, hipStream_t st);
 // K = 3 M|_out - 2 P on an output pattern: map[s] = M's strip with out's strip s key
 template <class T>

@@ -92,6 +92,9 @@ __global__ void k_add_sym(T* __restrict__ out, const T* __restrict__ v, const i6
 __device__ __forceinline__ void store4(float* p, const float (&v)[4]) {
   *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
 }
+__device__ __forceinline__ void store4(unsigned short* p, const unsigned short (&v)[4]) {
+  *reinterpret_cast<ushort4*>(p) = make_ushort4(v[0], v[1], v[2], v[3]);
+}
 __device__ __forceinline__ void store4(double* p, const double (&v)[4]) {
   reinterpret_cast<double2*>(p)[0] = make_double2(v[0], v[1]);
   reinterpret_cast<double2*>(p)[1] = make_double2(v[2], v[3]);
@@ -145,11 +148,29 @@ template <> struct Mma16<float> {
 // (column-major blocks, "C").
 // ---------------------------------------------------------------------------
 typedef short s4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ unsigned short bf16_rne(float f) {
   unsigned u = __float_as_uint(f);
   u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest even (finite inputs)
   return (unsigned short)(u >> 16);
+}
+
+// caller's block layout (FP64) -> bf16 strips, rounded through FP32 as the
+// FP32 strips would be: R keeps the layout, C transposes every 4x4 block
+__global__ void k_user_to_bf16(const double* __restrict__ user, unsigned short* __restrict__ outR,
+                               unsigned short* __restrict__ outC, const i64* __restrict__ su,
+                               const i64* __restrict__ ss, const i32* __restrict__ sh, i64 nsub) {
+  for (i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x; g < nsub * 16; g += (i64)gridDim.x * blockDim.x) {
+    const i64 sb = g >> 4;
+    const int e = (int)(g & 15), r = e >> 2, c = e & 3;
+    const int shape = sh[sb], rows = shape & 255, cols = (shape >> 8) & 255, stride = shape >> 16;
+    if (r < rows && c < cols) {
+      const unsigned short v = bf16_rne((float)user[su[sb] + (i64)r * stride + c]);
+      if (outR) outR[ss[sb] + r * 4 + c] = v;
+      if (outC) outC[ss[sb] + c * 4 + r] = v;
+    }
+  }
 }
 
 // fp32 strips -> bf16 copies: R keeps the layout, C transposes every 4x4 block
@@ -457,8 +478,11 @@ __device__ __forceinline__ void gbatch(char* ring, int rec_cur, int op_cur, int 
   }
 }
 
+// Occupancy: the FP32 instance fits 6 workgroups per CU (LDS 26.8 KB, at most
+// 80 VGPRs), which measured faster than 5 with deeper staging; the FP64
+// instance is bound by its accumulators to 4.
 template <class T, bool TA>
-__global__ void __launch_bounds__(256) k_gprod(const GTile* __restrict__ tiles, i64 ntiles,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) k_gprod(const GTile* __restrict__ tiles, i64 ntiles,
                                                const GStep* __restrict__ steps, const T* __restrict__ A,
                                                const T* __restrict__ B, T* __restrict__ C,
                                                const uint8_t* __restrict__ cmask, T alpha, T beta, int na_blk,
@@ -473,7 +497,8 @@ __global__ void __launch_bounds__(256) k_gprod(const GTile* __restrict__ tiles, 
   auto dslot = [&](int x) { return (x % L::NDS) * DSLOT; };
   auto rslot = [&](int x) { return L::NDS * DSLOT + (x % L::NRS) * RSLOT; };
   // output strips of each wavefront's 4 x GJ slots and their block masks
-  __shared__ int2 cinfo[GQ][4 * GJ];
+  __shared__ int cstr[GQ][4 * GJ];
+  __shared__ uint8_t cmsk[GQ][4 * GJ];
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -508,7 +533,10 @@ __global__ void __launch_bounds__(256) k_gprod(const GTile* __restrict__ tiles, 
     if (wave == 0 && lane < L::RLANES)
       for (int q = 0; q <= DA && q < nb; ++q) copy16(rec_src(q) + 16 * lane, ring + rslot(q));
     const int mk = my_cs >= 0 ? (int)cmask[my_cs] : 0;
-    if (lane < 4 * GJ) cinfo[wave][lane] = int2{my_cs, mk};
+    if (lane < 4 * GJ) {
+      cstr[wave][lane] = my_cs;
+      cmsk[wave][lane] = (uint8_t)mk;
+    }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     // batch q runs the MFMAs of q (q >= 0) and copies operands q+DA and
@@ -540,7 +568,7 @@ __global__ void __launch_bounds__(256) k_gprod(const GTile* __restrict__ tiles, 
         for (int v = 0; v < 4; ++v) {
           const int i = F64 ? v : (lane >> 4);
           const int rr = F64 ? (lane >> 4) : v;
-          const int2 ci = cinfo[wave][GJ * i + j];
+          const int2 ci = int2{cstr[wave][GJ * i + j], (int)cmsk[wave][GJ * i + j]};
           if (ci.x < 0) continue;
           const i64 idx = (i64)ci.x * 64 + tb * 16 + rr * 4 + cc;
           T o = ((ci.y >> tb) & 1) ? alpha * acc[j][v] : (T)0;
@@ -548,204 +576,24 @@ __global__ void __launch_bounds__(256) k_gprod(const GTile* __restrict__ tiles, 
           C[idx] = o;
         }
     }
-    // the next tile's prologue rewrites record slots and cinfo
+    // the next tile's prologue rewrites record slots and the slot table
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
-// Register-staged variant of the group-tile product (used for FP32): the
-// same tiles and steps, operands of batch q+1 loaded into registers while
-// batch q runs and stored to LDS at its end, 2 LDS slots, one batch ahead.
-// Measured on the 32768-atom RL16 chain it beats the direct-to-LDS copies in
-// FP32 (more resident workgroups at its LDS and register use); FP64 prefers
-// the direct copies (its staging registers would cost occupancy).
-// ---------------------------------------------------------------------------
-#ifndef LSDM_GSB_RS
-#define LSDM_GSB_RS 4
-#endif
-
-template <class T, bool TA>
-__global__ void __launch_bounds__(256) k_gprod_rs(const GTile* __restrict__ tiles, i64 ntiles,
-                                               const GStep* __restrict__ steps, const T* __restrict__ A,
-                                               const T* __restrict__ B, T* __restrict__ C,
-                                               const uint8_t* __restrict__ cmask, T alpha, T beta, int na_blk,
-                                               int nb_str, unsigned long long* __restrict__ queue) {
-  typedef typename Mma16<T>::acc_t acc_t;
-  constexpr bool F64 = sizeof(T) == 8;
-  constexpr int SB = LSDM_GSB_RS;
-  constexpr int AV = GROWS * 16;        // A values of one step
-  constexpr int BV = GJ * 64;           // B values of one step
-  constexpr int SV = AV + BV;
-  constexpr int VPL = 16 / (int)sizeof(T);
-  constexpr int PV = 64 * VPL;          // values of one 1 KB piece (16 bytes per lane)
-  constexpr int PPS = SV / PV;          // pieces per step
-  constexpr int SPW = SB / GQ;          // steps staged per wavefront and batch
-  constexpr int NPW = SPW * PPS;        // pieces per wavefront and batch
-  constexpr int RW = 32;                // dwords per record
-  constexpr int RLANES = SB * RW / 4;   // lanes that stage the records of a batch
-  static_assert(AV % PV == 0 && BV % PV == 0 && SB % GQ == 0 && RLANES <= 64, "staging layout");
-  __shared__ __attribute__((aligned(16))) T dbuf[2][SB * SV];
-  __shared__ __attribute__((aligned(16))) int rbuf[3][SB * RW];
-  // output strips of each wavefront's 4 x GJ slots and their block masks
-  __shared__ int2 cinfo[GQ][4 * GJ];
-
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int arow = lane & 15, ai = arow >> 2, ar = arow & 3, kk = lane >> 4;
-  const int a_off = (4 * wave + ai) * 16 + (TA ? (kk * 4 + ar) : (ar * 4 + kk));
-  const int b_off = ((lane & 15) >> 2) * 16 + kk * 4 + (lane & 3);
-  const int abit = 4 * wave + ai;
-  // tiles: see next_tile (per-XCD counters, then the other XCDs' tiles)
-  const int xcd = (int)(blockIdx.x & 7);
-  int victim = 0;
-  const i4v* recs = reinterpret_cast<const i4v*>(steps);
-  __shared__ i64 t_next;
-
-  for (;;) {
-    if (threadIdx.x == 0) t_next = next_tile(queue, ntiles, xcd, victim);
-    __syncthreads();
-    const i64 t = t_next;
-    if (t < 0) break;
-    const GTile* tp = tiles + uniform64(t);
-    const i64 s0 = tp->step0;
-    const int ns = tp->nsteps;
-    acc_t acc[GJ];
-#pragma unroll
-    for (int q = 0; q < GJ; ++q)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) acc[q][e] = (T)0;
-    const int nb = (ns + SB - 1) / SB;
-    // records of batch q: lane l < RLANES holds dwords 4l..4l+3 of the batch
-    auto load_records = [&](int q) -> i4v {
-      i4v v = {0, 0, 0, 0};
-      if (wave == 0 && lane < RLANES) v = recs[(s0 + (i64)SB * q) * (RW / 4) + lane];
-      return v;
-    };
-    auto store_records = [&](const i4v& v, int slot) {
-      if (wave == 0 && lane < RLANES) *reinterpret_cast<i4v*>(&rbuf[slot][4 * lane]) = v;
-    };
-    // operands of the batch whose records are in slot rslot: wavefront w
-    // stages steps SPW*w .. SPW*w+SPW-1, piece i of its share is step
-    // SPW*w + i / PPS, part i % PPS (1 KB) of that step's values
-    auto load_operands = [&](int rslot, i4v (&d)[NPW]) {
-      int idx[NPW];
-#pragma unroll
-      for (int i = 0; i < NPW; ++i) {
-        const int r = SPW * wave + i / PPS, part = i % PPS;
-        const int off = part * PV + lane * VPL;
-        idx[i] = part * PV < AV ? rbuf[rslot][r * RW + (off >> 4)] : rbuf[rslot][r * RW + GROWS + ((off - AV) >> 6)];
-      }
-#pragma unroll
-      for (int i = 0; i < NPW; ++i) {
-        const int part = i % PPS;
-        const int off = part * PV + lane * VPL;
-        const T* src = part * PV < AV ? A + (i64)min(max(idx[i], 0), na_blk - 1) * 16 + (off & 15)
-                                      : B + (i64)min(max(idx[i], 0), nb_str - 1) * 64 + ((off - AV) & 63);
-        d[i] = *reinterpret_cast<const i4v*>(src);
-      }
-    };
-    auto store_operands = [&](const i4v (&d)[NPW], int dslot) {
-#pragma unroll
-      for (int i = 0; i < NPW; ++i) {
-        const int r = SPW * wave + i / PPS, part = i % PPS;
-        *reinterpret_cast<i4v*>(&dbuf[dslot][r * SV + part * PV + lane * VPL]) = d[i];
-      }
-    };
-    // this wavefront's output strips (lane < 4 GJ: slot lane), staged in LDS
-    // with their block masks for the epilogue
-    const i32 my_cs = lane < 4 * GJ ? tp->cstrip[4 * GJ * wave + lane] : -1;
-    if (nb > 0) {
-      {
-        const i4v r0 = load_records(0);
-        const i4v r1 = nb > 1 ? load_records(1) : i4v{0, 0, 0, 0};
-        store_records(r0, 0);
-        store_records(r1, 1);
-      }
-      __syncthreads();
-      {
-        i4v d[NPW];
-        load_operands(0, d);
-        const int mk = my_cs >= 0 ? (int)cmask[my_cs] : 0;
-        store_operands(d, 0);
-        if (lane < 4 * GJ) cinfo[wave][lane] = int2{my_cs, mk};
-      }
-    } else if (lane < 4 * GJ) {
-      cinfo[wave][lane] = int2{my_cs, my_cs >= 0 ? (int)cmask[my_cs] : 0};
-    }
-    if (nb > 0) {
-      for (int q = 0; q < nb; ++q) {
-        __syncthreads();
-        const bool more_r = q + 2 < nb, more_d = q + 1 < nb;
-        i4v rn = {0, 0, 0, 0};
-        i4v dn[NPW];
-        if (more_r) rn = load_records(q + 2);
-        if (more_d) load_operands((q + 1) % 3, dn);
-        const int rs = q % 3, ds = q & 1;
-        const int nv = ns - SB * q;
-        // per step of the batch, read once per batch: lane r < SB holds the
-        // column quads with an active slot in this wavefront's rows (the OR of
-        // the four rows' GJ-bit fields, 0 past the tile's end), lane SB + r the
-        // row bits; one bit test per column quad then decides each MFMA
-        int mr = 0;
-        if (lane < SB) {
-          const uint32_t m = (uint32_t)rbuf[rs][lane * RW + GROWS + GJ + wave];
-          mr = lane < nv ? (int)((m | (m >> GJ) | (m >> (2 * GJ)) | (m >> (3 * GJ))) & ((1u << GJ) - 1u)) : 0;
-        } else if (lane < 2 * SB) {
-          mr = rbuf[rs][(lane - SB) * RW + GROWS + GJ + GQ];
-        }
-#pragma unroll 1
-        for (int r = 0; r < SB; ++r) {
-          const uint32_t jm = (uint32_t)__builtin_amdgcn_readlane(mr, r);
-          if (jm == 0u) continue;
-          const uint32_t rows = (uint32_t)__builtin_amdgcn_readlane(mr, SB + r);
-          const T* sA = &dbuf[ds][r * SV];
-          T av = sA[a_off];
-          av = ((rows >> abit) & 1u) ? av : (T)0;
-          T bv[GJ];
-#pragma unroll
-          for (int j = 0; j < GJ; ++j) bv[j] = sA[AV + j * 64 + b_off];
-#pragma unroll
-          for (int j = 0; j < GJ; ++j)
-            if (jm & (1u << j)) acc[j] = Mma16<T>::mma(av, bv[j], acc[j]);
-        }
-        if (more_d) store_operands(dn, (q + 1) & 1);
-        if (more_r) store_records(rn, (q + 2) % 3);
-      }
-    }
-    // epilogue: lane l, register v holds D[row][col]; f32 row = 4 (l/16) + v,
-    // f64 row = 4 v + l/16; col = l % 16 (block t = col / 4, c = col % 4)
-    {
-      const int col = lane & 15, tb = col >> 2, cc = col & 3;
-#pragma unroll
-      for (int j = 0; j < GJ; ++j)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = F64 ? v : (lane >> 4);
-          const int rr = F64 ? (lane >> 4) : v;
-          const int2 ci = cinfo[wave][GJ * i + j];
-          if (ci.x < 0) continue;
-          const i64 idx = (i64)ci.x * 64 + tb * 16 + rr * 4 + cc;
-          T o = ((ci.y >> tb) & 1) ? alpha * acc[j][v] : (T)0;
-          if (beta != (T)0) o += beta * C[idx];
-          C[idx] = o;
-        }
-    }
-    // the next tile's prologue reuses record slots 0, 1 and operand slot 0
-    __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------------------------
-// BF16 group-tile product: the staging of k_gprod with bf16 operands (8 bytes
-// per lane per piece) and v_mfma_f32_16x16x16_bf16, one instruction per
-// active column quad covering 4 consecutive steps: lane l holds A[l%16][4g..4g+3]
-// and B[4g..4g+3][l%16] for step slice g = l/16, i.e. one row of A_{r,k} (a
-// column of X_{k,r} for a transposed A, from the column-major copy) and one
-// column of a B block (column-major copy); D[4(l/16)+v][l%16] as for FP32.
-// A slice is zeroed where its step lies past the tile's end, its row has no
-// A block, or (for B) its column quad has no B strip.
+// BF16 group-tile product: register staging of bf16 operands (8 bytes per
+// lane per piece) and gfx950's v_mfma_f32_16x16x32_bf16, one instruction per
+// active column quad covering a batch's 8 steps: lane l holds
+// A[l%16][8g..8g+7] and B[8g..8g+7][l%16] for g = l/16, the k values of steps
+// 2g and 2g+1, i.e. one row of A_{r,k} (a column of X_{k,r} for a transposed
+// A, from the column-major copy) and one column of a B block (column-major
+// copy) of each of the two steps; D[4(l/16)+v][l%16] as for FP32.  A step's
+// half is zeroed where the step lies past the tile's end, its row has no A
+// block, or (for B) its column quad has no B strip.  The epilogue can also
+// write bf16 copies of the result (row-major and block-transposed) for the
+// products that take it as an operand, rounded from the FP32 value.
 // ---------------------------------------------------------------------------
 typedef int i2v __attribute__((ext_vector_type(2)));
 
@@ -754,10 +602,10 @@ __global__ void __launch_bounds__(256) k_gprod_bf16(const GTile* __restrict__ ti
                                                     const GStep* __restrict__ steps,
                                                     const unsigned short* __restrict__ A,
                                                     const unsigned short* __restrict__ B, float* __restrict__ C,
+                                                    unsigned short* __restrict__ outR, unsigned short* __restrict__ outC,
                                                     const uint8_t* __restrict__ cmask, float alpha, float beta,
                                                     unsigned long long* __restrict__ queue) {
-  constexpr int SB = 8;                 // steps per batch: two MFMA groups of KG steps
-  constexpr int KG = 4;
+  constexpr int SB = 8;                 // steps per batch: one MFMA of K = 32 per column quad
   constexpr int AV = GROWS * 16;
   constexpr int BV = GJ * 64;
   constexpr int SV = AV + BV;
@@ -768,10 +616,11 @@ __global__ void __launch_bounds__(256) k_gprod_bf16(const GTile* __restrict__ ti
   constexpr int NPW = SPW * PPS;
   constexpr int RW = 32;
   constexpr int RLANES = SB * RW / 4;
-  static_assert(AV % PV == 0 && BV % PV == 0 && SB % GQ == 0 && SB % KG == 0 && RLANES <= 64, "staging layout");
+  static_assert(AV % PV == 0 && BV % PV == 0 && SB % GQ == 0 && SB == 2 * GQ && RLANES <= 64, "staging layout");
   __shared__ __attribute__((aligned(16))) unsigned short dbuf[2][SB * SV];
   __shared__ __attribute__((aligned(16))) int rbuf[3][SB * RW];
-  __shared__ int2 cinfo[GQ][4 * GJ];
+  __shared__ int cstr[GQ][4 * GJ];
+  __shared__ uint8_t cmsk[GQ][4 * GJ];
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -846,10 +695,14 @@ __global__ void __launch_bounds__(256) k_gprod_bf16(const GTile* __restrict__ ti
         load_operands(0, d);
         const int mk = my_cs >= 0 ? (int)cmask[my_cs] : 0;
         store_operands(d, 0);
-        if (lane < 4 * GJ) cinfo[wave][lane] = int2{my_cs, mk};
+        if (lane < 4 * GJ) {
+          cstr[wave][lane] = my_cs;
+          cmsk[wave][lane] = (uint8_t)mk;
+        }
       }
     } else if (lane < 4 * GJ) {
-      cinfo[wave][lane] = int2{my_cs, my_cs >= 0 ? (int)cmask[my_cs] : 0};
+      cstr[wave][lane] = my_cs;
+      cmsk[wave][lane] = (uint8_t)(my_cs >= 0 ? cmask[my_cs] : 0);
     }
     for (int q = 0; q < nb; ++q) {
       __syncthreads();
@@ -860,31 +713,42 @@ __global__ void __launch_bounds__(256) k_gprod_bf16(const GTile* __restrict__ ti
       if (more_d) load_operands((q + 1) % 3, dn);
       const int rs = q % 3, ds = q & 1;
       const int nv = ns - SB * q;
-#pragma unroll 1
-      for (int g = 0; g < SB / KG; ++g) {
-        const int rl = KG * g + ks;                      // this lane's step in the batch
-        const int* rec = &rbuf[rs][rl * RW];
-        const bool valid = rl < nv;
-        const uint32_t m_l = valid ? (uint32_t)rec[GROWS + GJ + wave] : 0u;
-        const uint32_t rows_l = (uint32_t)rec[GROWS + GJ + GQ];
-        const uint32_t bcols_l = (uint32_t)rec[GROWS + GJ + GQ + 1];
+      {
+        // one v_mfma_f32_16x16x32_bf16 per active column quad covers the
+        // batch's 8 steps: lane group ks holds steps 2 ks and 2 ks + 1 (8
+        // consecutive k values), each half zeroed on its own where its step
+        // lies past the tile's end, its row has no A block or its column no
+        // B strip
+        const int rl0 = 2 * ks, rl1 = rl0 + 1;
+        const int* rec0 = &rbuf[rs][rl0 * RW];
+        const int* rec1 = &rbuf[rs][rl1 * RW];
+        const bool v0 = rl0 < nv, v1 = rl1 < nv;
+        const uint32_t m_l = (v0 ? (uint32_t)rec0[GROWS + GJ + wave] : 0u) | (v1 ? (uint32_t)rec1[GROWS + GJ + wave] : 0u);
         const uint32_t colany = (uint32_t)__builtin_amdgcn_readlane((int)m_l, 0) |
                                 (uint32_t)__builtin_amdgcn_readlane((int)m_l, 16) |
                                 (uint32_t)__builtin_amdgcn_readlane((int)m_l, 32) |
                                 (uint32_t)__builtin_amdgcn_readlane((int)m_l, 48);
-        if (colany == 0u) continue;
-        const unsigned short* sS = &dbuf[ds][rl * SV];
-        s4 av = *reinterpret_cast<const s4*>(sS + a_off);
-        if (!(valid && ((rows_l >> abit) & 1u))) av = s4{0, 0, 0, 0};
-        s4 bv[GJ];
+        if (colany != 0u) {
+          const uint32_t rows0 = (uint32_t)rec0[GROWS + GJ + GQ], rows1 = (uint32_t)rec1[GROWS + GJ + GQ];
+          const uint32_t bc0 = (uint32_t)rec0[GROWS + GJ + GQ + 1], bc1 = (uint32_t)rec1[GROWS + GJ + GQ + 1];
+          const unsigned short* sS0 = &dbuf[ds][rl0 * SV];
+          const unsigned short* sS1 = &dbuf[ds][rl1 * SV];
+          s4 a0 = *reinterpret_cast<const s4*>(sS0 + a_off);
+          s4 a1 = *reinterpret_cast<const s4*>(sS1 + a_off);
+          if (!(v0 && ((rows0 >> abit) & 1u))) a0 = s4{0, 0, 0, 0};
+          if (!(v1 && ((rows1 >> abit) & 1u))) a1 = s4{0, 0, 0, 0};
+          const bf8 av = __builtin_bit_cast(bf8, __builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7));
 #pragma unroll
-        for (int j = 0; j < GJ; ++j) {
-          bv[j] = *reinterpret_cast<const s4*>(sS + AV + j * 64 + b_off);
-          if (!((bcols_l >> j) & 1u)) bv[j] = s4{0, 0, 0, 0};
+          for (int j = 0; j < GJ; ++j) {
+            if (!((colany >> j) & COL)) continue;
+            s4 b0 = *reinterpret_cast<const s4*>(sS0 + AV + j * 64 + b_off);
+            s4 b1 = *reinterpret_cast<const s4*>(sS1 + AV + j * 64 + b_off);
+            if (!((bc0 >> j) & 1u)) b0 = s4{0, 0, 0, 0};
+            if (!((bc1 >> j) & 1u)) b1 = s4{0, 0, 0, 0};
+            const bf8 bv = __builtin_bit_cast(bf8, __builtin_shufflevector(b0, b1, 0, 1, 2, 3, 4, 5, 6, 7));
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[j], 0, 0, 0);
+          }
         }
-#pragma unroll
-        for (int j = 0; j < GJ; ++j)
-          if ((colany >> j) & COL) acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv[j], acc[j], 0, 0, 0);
       }
       if (more_d) store_operands(dn, (q + 1) & 1);
       if (more_r) store_records(rn, (q + 2) % 3);
@@ -896,12 +760,16 @@ __global__ void __launch_bounds__(256) k_gprod_bf16(const GTile* __restrict__ ti
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int i = lane >> 4, rr = v;
-          const int2 ci = cinfo[wave][GJ * i + j];
+          const int2 ci = int2{cstr[wave][GJ * i + j], (int)cmsk[wave][GJ * i + j]};
           if (ci.x < 0) continue;
           const i64 idx = (i64)ci.x * 64 + tb * 16 + rr * 4 + cc;
           float o = ((ci.y >> tb) & 1) ? alpha * acc[j][v] : 0.f;
           if (beta != 0.f) o += beta * C[idx];
-          C[idx] = o;
+          if (C) C[idx] = o;
+          // bf16 operand copies for later products, rounded from the FP32
+          // result as a separate conversion pass would
+          if (outR) outR[idx] = bf16_rne(o);
+          if (outC) outC[(i64)ci.x * 64 + tb * 16 + cc * 4 + rr] = bf16_rne(o);
         }
     }
     __syncthreads();
@@ -1149,6 +1017,7 @@ void fill(T* p, i64 n, T v, hipStream_t st) {
 }
 template void fill<double>(double*, i64, double, hipStream_t);
 template void fill<float>(float*, i64, float, hipStream_t);
+template void fill<unsigned short>(unsigned short*, i64, unsigned short, hipStream_t);
 
 template <class T>
 void user_to_strip(const lsdm_pattern* p, const double* user, T* strip, double scale, hipStream_t st) {
@@ -1199,6 +1068,7 @@ void sym_fill(const lsdm_pattern* p, T* data, hipStream_t st) {
 }
 template void sym_fill<double>(const lsdm_pattern*, double*, hipStream_t);
 template void sym_fill<float>(const lsdm_pattern*, float*, hipStream_t);
+template void sym_fill<unsigned short>(const lsdm_pattern*, unsigned short*, hipStream_t);
 
 // Grid of the group kernel: as many workgroups as are resident at once (so
 // every workgroup of an XCD walks its tile range in step with the others), a
@@ -1239,25 +1109,14 @@ void product(const lsdm_plan* pl, const T* A, const T* B, T* C, double alpha, do
   const dim3 b(256);
   // operand array bounds for the index clamp (a plan with steps has both)
   const int na = (int)std::max<i64>(1, pl->A->n_strips * 4), nbs = (int)std::max<i64>(1, pl->B->n_strips);
-  if constexpr (sizeof(T) == 4) {
-    unsigned long long* q = pl->d_queue.as<unsigned long long>();
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, q, 8);
-    if (pl->transA)
-      hipLaunchKernelGGL((k_gprod_rs<T, true>), dim3(gproduct_grid(k_gprod_rs<T, true>, pl->n_gtiles)), b, 0, st, Tl,
-                         pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta, na, nbs, q);
-    else
-      hipLaunchKernelGGL((k_gprod_rs<T, false>), dim3(gproduct_grid(k_gprod_rs<T, false>, pl->n_gtiles)), b, 0, st,
-                         Tl, pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta, na, nbs, q);
-  } else {
-    unsigned long long* q = pl->d_queue.as<unsigned long long>();
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, q, 8);
-    if (pl->transA)
-      hipLaunchKernelGGL((k_gprod<T, true>), dim3(gproduct_grid(k_gprod<T, true>, pl->n_gtiles)), b, 0, st, Tl,
-                         pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta, na, nbs, q);
-    else
-      hipLaunchKernelGGL((k_gprod<T, false>), dim3(gproduct_grid(k_gprod<T, false>, pl->n_gtiles)), b, 0, st, Tl,
-                         pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta, na, nbs, q);
-  }
+  unsigned long long* q = pl->d_queue.as<unsigned long long>();
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, q, 8);
+  if (pl->transA)
+    hipLaunchKernelGGL((k_gprod<T, true>), dim3(gproduct_grid(k_gprod<T, true>, pl->n_gtiles)), b, 0, st, Tl,
+                       pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta, na, nbs, q);
+  else
+    hipLaunchKernelGGL((k_gprod<T, false>), dim3(gproduct_grid(k_gprod<T, false>, pl->n_gtiles)), b, 0, st, Tl,
+                       pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta, na, nbs, q);
 }
 template void product<double>(const lsdm_plan*, const double*, const double*, double*, double, double, hipStream_t);
 template void product<float>(const lsdm_plan*, const float*, const float*, float*, double, double, hipStream_t);
@@ -1343,8 +1202,16 @@ void to_bf16(const float* in, unsigned short* outR, unsigned short* outC, i64 n,
   hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(n)), dim3(256), 0, st, in, outR, outC, n);
 }
 
+void user_to_bf16(const lsdm_pattern* p, const double* user, unsigned short* outR, unsigned short* outC,
+                  hipStream_t st) {
+  ensure_maps(const_cast<lsdm_pattern*>(p));
+  if (p->n_sub == 0) return;
+  hipLaunchKernelGGL(k_user_to_bf16, dim3(grid_for(p->n_sub * 16)), dim3(256), 0, st, user, outR, outC,
+                     p->d_sub_user.as<i64>(), p->d_sub_strip.as<i64>(), p->d_sub_shape.as<i32>(), p->n_sub);
+}
+
 void product_bf16(const lsdm_plan* pl, const unsigned short* A, const unsigned short* B, float* C, double alpha,
-                  double beta, hipStream_t st) {
+                  double beta, hipStream_t st, unsigned short* outR, unsigned short* outC) {
   if (pl->n_gtiles == 0) return;
   const GTile* Tl = pl->d_gtiles.as<GTile>();
   const GStep* S = pl->d_gsteps.as<GStep>();
@@ -1354,10 +1221,10 @@ void product_bf16(const lsdm_plan* pl, const unsigned short* A, const unsigned s
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, q, 8);
   if (pl->transA)
     hipLaunchKernelGGL((k_gprod_bf16<true>), dim3(gproduct_grid(k_gprod_bf16<true>, pl->n_gtiles)), b, 0, st, Tl,
-                       pl->n_gtiles, S, A, B, C, cm, (float)alpha, (float)beta, q);
+                       pl->n_gtiles, S, A, B, C, outR, outC, cm, (float)alpha, (float)beta, q);
   else
     hipLaunchKernelGGL((k_gprod_bf16<false>), dim3(gproduct_grid(k_gprod_bf16<false>, pl->n_gtiles)), b, 0, st, Tl,
-                       pl->n_gtiles, S, A, B, C, cm, (float)alpha, (float)beta, q);
+                       pl->n_gtiles, S, A, B, C, outR, outC, cm, (float)alpha, (float)beta, q);
 }
 
 template <class T>

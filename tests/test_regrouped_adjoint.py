@@ -1,9 +1,14 @@
-"""The symmetric-mode adjoint of the GPU chain, assembled from the oracle's
-plain truncated products (CPU): with S, H, L symmetric the gradient of eq. 3
-is taken as
+"""Groupings of the symmetric-mode adjoint, assembled from the oracle's plain
+truncated products (CPU).  The chain runs the second one (Y = P_M(HX) formed
+once); the first one is the grouping it ran before.  With S, H, L symmetric
+the gradient of eq. 3 is taken as
 
     Mbar = -4 P_M(X^T H),  Xbar = -4 P_X(H M),
     dE/dL = P_L(Mbar X) + V + V^T,   V = 6 P_L(H X) + P_L(Xbar S),
+
+or, forming Y = P_M(H X) once,
+
+    dE/dL = -4 P_L(X^T Y) + V + V^T,   V = 6 P_L(Y) + P_L(Xbar S),
 
 with X = P_X(L S) and M = P_M(X L) on the chain's ranges.  Every truncation
 has to keep what L's range reaches for this to equal the gradient of eq. 3;
@@ -51,6 +56,53 @@ def _grouped(L, S, H, pX, pM, pXbar=None, pMbar=None):
     V.val *= 6.0
     oracle.multiply(Xbar, S, pL, out=V)
     return B3.val, V.val, oracle.transpose(V, pL).val
+
+
+def _grouped_y(L, S, H, pX, pM, pY=None):
+    """dE/dL by the grouping that forms Y = P_M(H X) once:
+    -4 P_L(X^T Y) + V + V^T with V = 6 P_L(Y) + P_L(Xbar S), Xbar = -4 P_X(H M);
+    pY overrides Y's pattern (to show that a shorter range is detected)."""
+    pL = L.pattern
+    X = oracle.multiply(L, S, pX)
+    M = oracle.multiply(X, L, pM)
+    Y = oracle.multiply(H, X, pY or pM)
+    Xbar = oracle.multiply(H, M, pX)
+    Xbar.val *= -4.0
+    B3 = oracle.multiply(oracle.transpose(X, pX), Y, pL)
+    B3.val *= -4.0
+    V = oracle.project(Y, pL)
+    V.val *= 6.0
+    oracle.multiply(Xbar, S, pL, out=V)
+    return B3.val, V.val, oracle.transpose(V, pL).val
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_y_grouping_equals_gradient(name):
+    """The grouping the symmetric-mode chain runs: Y = P_M(HX) serves both
+    the X^T H X term (as X^T Y on L's range) and the 6 HX term (as Y's
+    projection on L's range)."""
+    s, rS, rH, rL = CASES[name]()
+    R = oracle.chain_ranges(rS, rH, rL)
+    inp = oracle.make_inputs(s, rS, rH, rL)
+    L, S, H = inp["L"], inp["S"], inp["H"]
+    pX, pM = oracle.pattern(s, R["X"]), oracle.pattern(s, R["M"])
+    Gref = oracle.lnv_gradient(L, S, H, rS, rH, rL)
+    assert _rel(sum(_grouped_y(L, S, H, pX, pM)), Gref.val) <= 1e-13
+
+
+@pytest.mark.parametrize("name", ["si64_jitter_rl16", "open_cluster_ragged", "si64_h_beyond_lsl"])
+def test_y_grouping_ranges_without_decay(name):
+    """Unit-size symmetric values at every range: Y on M's range gives the
+    gradient to rounding, Y on a range 4 bohr shorter does not."""
+    s, rS, rH, rL = CASES[name]()
+    R = oracle.chain_ranges(rS, rH, rL)
+    rng = np.random.default_rng(5)
+    L, S, H = (_sym_random(oracle.pattern(s, r), rng) for r in (rL, rS, rH))
+    pX, pM = oracle.pattern(s, R["X"]), oracle.pattern(s, R["M"])
+    Gref = oracle.lnv_gradient(L, S, H, rS, rH, rL).val
+    assert _rel(sum(_grouped_y(L, S, H, pX, pM)), Gref) <= 1e-13
+    short = _grouped_y(L, S, H, pX, pM, pY=oracle.pattern(s, R["M"] - 4.0))
+    assert _rel(sum(short), Gref) > 1e-6
 
 
 @pytest.mark.parametrize("name", list(CASES))
