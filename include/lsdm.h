@@ -182,8 +182,8 @@ enum {
    * of their output strips and the other half is filled with transposes, and
    * the adjoint takes dE/dL as V + V^T - 4 X^T H X with X = LS and
    * V = 6 HX - 4 HMS (the same terms as the gradient of eq. 3, regrouped;
-   * X^T H X on one half).  Together: 48 % fewer flops per energy-and-gradient
-   * step on the 32,768-atom Si cell, ranges 8/12/16.  Every L passed to a handle made with this flag
+   * HX formed once on M's range and reused for both terms, X^T H X on one
+   * half).  Every L passed to a handle made with this flag
    * (also L + tD in a line search) must be symmetric; for a non-symmetric L
    * the results are those of the computed half mirrored, not of eq. 3. */
   LSDM_LNV_SYMMETRIC = 1
@@ -267,7 +267,8 @@ int lsdm_lnv_profile(lsdm_lnv* lnv, int enable);
  * launches and the useful flops of one launch; clears the record.  F1-F3 make
  * X = LS, M = XL and P = XM; B1 Mbar = X^T Pbar, B2 Xbar = Pbar M, then
  * B3 Xbar += Mbar L, B4 dE/dL = X^T Mbar, B5 dE/dL += Xbar S, or in symmetric
- * mode B3 dE/dL = Mbar X, B4 V = 6 HX, B5 V += Xbar S (dE/dL += V + V^T). */
+ * mode B1 Y = HX, B3 dE/dL = -4 X^T Y, B5 V += Xbar S with V = 6 Y on L's
+ * range (a projection: B4 has no launches and no flops) and dE/dL += V + V^T. */
 int lsdm_lnv_profile_read(lsdm_lnv* lnv, double* ms, int64_t* launches, double* flops);
 void lsdm_lnv_destroy(lsdm_lnv* lnv);
 

@@ -15,16 +15,17 @@
 // the adjoint yields dE/dL of eq. 3 itself: 6 (HLS + SLH) - 4 (HLSLS + SLHLS + SLSLH).
 // Symmetric mode (S, H, L symmetric, so Xᵀ = SL and M = LSL are known
 // transposes) groups the same terms as dE/dL = V + Vᵀ - 4 XᵀHX with
-// V = 6 HX - 4 HMS, each on L's range:
-//             B1  Mbar = P_M(X^T Pbar)            (no 6H)
+// V = 6 HX - 4 HMS, each on L's range, and forms HX once:
+//             B1  Y    = P_M(H X)
 //             B2  Xbar = P_X(Pbar M)              (= -4 HM)
-//             B3  Lbar = P_L(Mbar X)              (= -4 XᵀHX, symmetric: half)
-//             B4  V    = P_L(6 H X)
+//             B3  Lbar = -4 P_L(X^T Y)            (= -4 XᵀHX, symmetric: half)
+//             B4  V    = 6 P_L(Y)                 (a projection, no product)
 //             B5  V   += P_L(Xbar S)
 //             Lbar += V + Vᵀ, then the dropped half is mirrored.
 // Every truncation keeps what L's range reaches: X's range holds all of
-// P_X(HM) that (HM)S needs on L, and M's range all of P_M(XᵀH) that (XᵀH)X
-// needs on L, so the regrouped chain equals the one above up to rounding.
+// P_X(HM) that (HM)S needs on L, and M's range all of HX (nonzero within
+// R_H + R_X) that Xᵀ(HX) needs on L, so the regrouped chain equals the one
+// above up to rounding.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -278,11 +279,12 @@ static void lnv_build(lsdm_lnv* L) {
   const bool h = L->sym;
   L->F2 = make_plan(L->pX, 0, L->pL, 0, L->pM, h);
   L->F3 = make_plan(L->pX, 0, L->pM, 0, L->pH, h);
-  L->B1 = make_plan(L->pX, 1, L->pH, 0, L->pM);
+  // B1: Mbar = X^T Pbar on M's range, or in symmetric mode Y = H X there
+  L->B1 = h ? make_plan(L->pH, 0, L->pX, 0, L->pM) : make_plan(L->pX, 1, L->pH, 0, L->pM);
   L->B2 = make_plan(L->pH, 0, L->pM, 0, L->pX);
   if (h) {
-    L->B3 = make_plan(L->pM, 0, L->pX, 0, L->pL, true);
-    L->B4 = make_plan(L->pH, 0, L->pX, 0, L->pL);
+    L->B3 = make_plan(L->pX, 1, L->pM, 0, L->pL, true);    // X^T Y, half
+    L->B4 = nullptr;                                        // V = 6 P_L(Y): a projection
   } else {
     L->B3 = make_plan(L->pM, 0, L->pL, 0, L->pX);
     L->B4 = make_plan(L->pX, 1, L->pM, 0, L->pL);
@@ -293,6 +295,10 @@ static void lnv_build(lsdm_lnv* L) {
   // blocks of K are -2 P alone and carry no 6H into Mbar
   const std::vector<i64> h2m = strip_map(L->sys, L->pH, L->pM, nullptr);
   L->d_h2m.upload(h2m.data(), sizeof(i64) * h2m.size());
+  if (h) {   // L strip -> M strip (Y's projection on L's range; M's range holds L's)
+    const std::vector<i64> l2y = strip_map(L->sys, L->pL, L->pM, "L range exceeds the LSL range");
+    L->d_l2y.upload(l2y.data(), sizeof(i64) * l2y.size());
+  }
   auto ws = [](DevBuf& b, const lsdm_pattern* p) { b.alloc(strip_bytes(p, sizeof(double))); };
   ws(L->wL, L->pL);
   ws(L->wS, L->pS);
@@ -374,17 +380,20 @@ static void lnv_backward(lsdm_lnv* L, double* dG, hipStream_t st) {
   T* wMb = L->wMb.as<T>();
   T* wXb = L->wXb.as<T>();
   T* wLb = L->wLb.as<T>();
-  chain_product<T>(L, 3, wX, wH, wMb, -4.0, 0.0, st);    // Mbar = X^T Pbar,  Pbar = -4H (every M strip written)
-  chain_product<T>(L, 4, wH, wM, wXb, -4.0, 0.0, st);    // Xbar  = Pbar M
   if (!L->sym) {
+    chain_product<T>(L, 3, wX, wH, wMb, -4.0, 0.0, st);  // Mbar = X^T Pbar,  Pbar = -4H (every M strip written)
+    chain_product<T>(L, 4, wH, wM, wXb, -4.0, 0.0, st);  // Xbar  = Pbar M
     scatter_h<T>(L, wH, wMb, 6.0, st);                   // Mbar += 3 Kbar = 6H on H's range
     chain_product<T>(L, 5, wMb, wL, wXb, 1.0, 1.0, st);  // Xbar += Mbar L
     chain_product<T>(L, 6, wX, wMb, wLb, 1.0, 0.0, st);  // Lbar  = X^T Mbar
     chain_product<T>(L, 7, wXb, wS, wLb, 1.0, 1.0, st);  // Lbar += Xbar S
   } else {
     T* wV = L->wV.as<T>();
-    chain_product<T>(L, 5, wMb, wX, wLb, 1.0, 0.0, st);  // Lbar = Mbar X = -4 X^T H X (half)
-    chain_product<T>(L, 6, wH, wX, wV, 6.0, 0.0, st);    // V = 6 H X
+    T* wY = wMb;                                         // Y = H X on M's range (Mbar's workspace)
+    chain_product<T>(L, 3, wH, wX, wY, 1.0, 0.0, st);    // Y = H X
+    chain_product<T>(L, 4, wH, wM, wXb, -4.0, 0.0, st);  // Xbar = -4 H M
+    chain_product<T>(L, 5, wX, wY, wLb, -4.0, 0.0, st);  // Lbar = -4 X^T Y = -4 X^T H X (half)
+    project_strips<T>(L->pL, L->d_l2y.as<i64>(), wY, wV, 6.0, st);   // V = 6 P_L(Y) = 6 H X on L
     chain_product<T>(L, 7, wXb, wS, wV, 1.0, 1.0, st);   // V += Xbar S = -4 H M S
     add_sym<T>(L->pL, wV, wLb, st);                      // Lbar += V + V^T
     sym_fill<T>(L->pL, wLb, st);
@@ -483,11 +492,13 @@ static void lnv_backward_bf16(lsdm_lnv* L, double* dG, hipStream_t st) {
     chain_product_bf16(L, 7, h(XbR), h(SC), wLb, 1.0, 1.0, st);   // Lbar += Xbar S
   } else {
     float* wV = L->wV.as<float>();
-    // Mbar and Xbar are operands only: their bf16 copies come from the epilogues
-    chain_product_bf16(L, 3, h(XC), h(HC), nullptr, -4.0, 0.0, st, h(MbR), nullptr);   // Mbar = X^T Pbar
+    float* wY = wMb;
+    // Y = H X: FP32 for its projection, block-transposed bf16 copy as the
+    // B operand of X^T Y (in Mbar's bf16 slot); Xbar is an operand only
+    chain_product_bf16(L, 3, h(HR), h(XC), wY, 1.0, 0.0, st, nullptr, h(MbC));         // Y = H X
     chain_product_bf16(L, 4, h(HR), h(MC), nullptr, -4.0, 0.0, st, h(XbR), nullptr);   // Xbar = Pbar M
-    chain_product_bf16(L, 5, h(MbR), h(XC), wLb, 1.0, 0.0, st); // Lbar = Mbar X (half)
-    chain_product_bf16(L, 6, h(HR), h(XC), wV, 6.0, 0.0, st);   // V = 6 H X
+    chain_product_bf16(L, 5, h(XC), h(MbC), wLb, -4.0, 0.0, st); // Lbar = -4 X^T Y (half)
+    project_strips<float>(L->pL, L->d_l2y.as<i64>(), wY, wV, 6.0, st);                  // V = 6 P_L(Y)
     chain_product_bf16(L, 7, h(XbR), h(SC), wV, 1.0, 1.0, st);  // V += Xbar S
     add_sym<float>(L->pL, wV, wLb, st);                           // Lbar += V + V^T
     sym_fill<float>(L->pL, wLb, st);
@@ -559,7 +570,8 @@ static void lnv_backward_rc(lsdm_lnv* L, double* dG, hipStream_t st) {
   double* wMb = L->wMb.as<double>();
   double* wXb = L->wXb.as<double>();
   double* wLb = L->wLb.as<double>();
-  rc_step(L, 3, wX, r(RX), wH, r(RH), wMb, -4.0, 0.0, st);     // Mbar = X^T Pbar
+  if (L->sym) rc_step(L, 3, wH, r(RH), wX, r(RX), wMb, 1.0, 0.0, st);   // Y = H X (in Mbar's workspace)
+  else rc_step(L, 3, wX, r(RX), wH, r(RH), wMb, -4.0, 0.0, st);          // Mbar = X^T Pbar
   if (!L->sym) scatter_h<double>(L, wH, wMb, 6.0, st);         // Mbar += 6H
   offsite_f32(L->pM, wMb, r(RMb), st);
   rc_step(L, 4, wH, r(RH), wM, r(RM), wXb, -4.0, 0.0, st);     // Xbar = Pbar M
@@ -571,8 +583,8 @@ static void lnv_backward_rc(lsdm_lnv* L, double* dG, hipStream_t st) {
   } else {
     double* wV = L->wV.as<double>();
     offsite_f32(L->pX, wXb, r(RXb), st);
-    rc_step(L, 5, wMb, r(RMb), wX, r(RX), wLb, 1.0, 0.0, st);  // Lbar = Mbar X (half)
-    rc_step(L, 6, wH, r(RH), wX, r(RX), wV, 6.0, 0.0, st);     // V = 6 H X
+    rc_step(L, 5, wX, r(RX), wMb, r(RMb), wLb, -4.0, 0.0, st); // Lbar = -4 X^T Y (half)
+    project_strips<double>(L->pL, L->d_l2y.as<i64>(), wMb, wV, 6.0, st);   // V = 6 P_L(Y)
     rc_step(L, 7, wXb, r(RXb), wS, r(RS), wV, 1.0, 1.0, st);   // V += Xbar S
     add_sym<double>(L->pL, wV, wLb, st);                         // Lbar += V + V^T
     sym_fill<double>(L->pL, wLb, st);
@@ -857,7 +869,8 @@ int lsdm_lnv_info(const lsdm_lnv* L, int grad, int64_t* n_triples, double* flops
     double fl = 0;
     for (auto p : f) { nt += p->n_triples; fl += p->flops; }
     if (grad)
-      for (auto p : b) { nt += p->n_triples; fl += p->flops; }
+      for (auto p : b)
+        if (p) { nt += p->n_triples; fl += p->flops; }
     if (n_triples) *n_triples = nt;
     if (flops) *flops = fl;
   });
@@ -1165,7 +1178,7 @@ int lsdm_lnv_profile_read(lsdm_lnv* L, double* ms, int64_t* launches, double* fl
     for (int w = 0; w < 8; ++w) {
       ms[w] = 0.0;
       launches[w] = 0;
-      flops[w] = chain_plan(L, w)->flops;
+      flops[w] = chain_plan(L, w) ? chain_plan(L, w)->flops : 0.0;   // symmetric mode has no B4 product
     }
     if (L->ev_used) HIP_CHECK(hipEventSynchronize(L->ev_pool[L->ev_used - 1]));
     for (size_t k = 0; k < L->ev_prod.size(); ++k) {

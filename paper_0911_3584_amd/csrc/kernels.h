@@ -50,6 +50,9 @@ template <class T> void kassembly(const lsdm_lnv* L, const T* M, const T* P, dou
 template <class T>
 void kassembly_on(const lsdm_pattern* out, const i64* map, const T* M, const T* P, double* K, hipStream_t st);
 template <class T> void scatter_h(const lsdm_lnv* L, const T* H, T* Mb, double scale, hipStream_t st);
+// o = scale * P_out(in) in strip layout: out's strip s from in's strip map[s], masked to out's blocks
+template <class T>
+void project_strips(const lsdm_pattern* out, const i64* map, const T* in, T* o, double scale, hipStream_t st);
 // out[0] = scale * sum a[i] b[i]; partial holds 2 * DOT_BLOCKS doubles
 void dot(const double* a, const double* b, i64 n, double scale, double* partial, double* out, hipStream_t st);
 // out = a x + b y, n doubles

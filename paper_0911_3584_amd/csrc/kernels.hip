@@ -926,6 +926,18 @@ __global__ void k_kassembly(const T* __restrict__ M, const T* __restrict__ P, do
   }
 }
 
+// out = scale * P_out(in): every strip of `out`'s pattern takes the strip
+// map[s] of `in` (a pattern containing out's), masked to out's blocks
+template <class T>
+__global__ void k_project_strips(const T* __restrict__ in, T* __restrict__ out, const i64* __restrict__ map,
+                                 const uint8_t* __restrict__ omask, i64 nout, T scale) {
+  for (i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x; g < nout * 64; g += (i64)gridDim.x * blockDim.x) {
+    const i64 st = g >> 6;
+    const int e = (int)(g & 63);
+    out[g] = ((omask[st] >> (e >> 4)) & 1) ? scale * in[map[st] * 64 + e] : (T)0;
+  }
+}
+
 // Mbar += scale * H on the blocks of H inside M's pattern (H's strips mapped
 // into M's strips; blocks outside M's, which LSL cannot reach, are skipped,
 // so Mbar stays zero off its pattern)
@@ -1253,6 +1265,16 @@ void scatter_h(const lsdm_lnv* L, const T* H, T* Mb, double scale, hipStream_t s
 }
 template void scatter_h<double>(const lsdm_lnv*, const double*, double*, double, hipStream_t);
 template void scatter_h<float>(const lsdm_lnv*, const float*, float*, double, hipStream_t);
+
+template <class T>
+void project_strips(const lsdm_pattern* out, const i64* map, const T* in, T* o, double scale, hipStream_t st) {
+  const i64 n = out->n_strips;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_project_strips<T>, dim3(grid_for(n * 64)), dim3(256), 0, st, in, o, map,
+                     out->d_smask.as<uint8_t>(), n, (T)scale);
+}
+template void project_strips<double>(const lsdm_pattern*, const i64*, const double*, double*, double, hipStream_t);
+template void project_strips<float>(const lsdm_pattern*, const i64*, const float*, float*, double, hipStream_t);
 
 // out = a x + b y (element-wise; out may be x or y)
 __global__ void k_lincomb(double* out, const double* x, const double* y, double a, double b, i64 n) {

@@ -215,7 +215,8 @@ struct lsdm_lnv {
   double rS = 0, rH = 0, rL = 0;
   // symmetric mode: L, S, H are symmetric, so M and P are computed on one
   // half (F2, F3 half-output plans) and mirrored, and the adjoint takes dE/dL
-  // as V + V^T - 4 X^T H X (B3 half-output; B4, B5 make V on all of L)
+  // as V + V^T - 4 X^T Y with Y = HX on M's range (B1), the last term a
+  // half-output product (B3), V = 6 Y on L plus Xbar S (B5); B4 is null
   bool sym = false;
   lsdm_pattern *pS = nullptr, *pH = nullptr, *pL = nullptr, *pX = nullptr, *pM = nullptr;
   lsdm_plan *F1 = nullptr, *F2 = nullptr, *F3 = nullptr;
@@ -226,7 +227,8 @@ struct lsdm_lnv {
   lsdm::DevBuf wV;                  // symmetric mode: V = 6 H X - 4 H M S on L's pattern
   lsdm::DevBuf wE;                  // partial sums for the energy
   // map from H's strips to M's strips (K assembly and 6H into Mbar)
-  lsdm::DevBuf d_h2m;               // i64 per H strip: M strip index
+  lsdm::DevBuf d_h2m;               // i64 per H strip: M strip index (-1: none)
+  lsdm::DevBuf d_l2y;               // symmetric mode: i64 per L strip, the M strip of Y = HX to project
   // bf16 operand copies (allocated on first BF16 use): R = row-major blocks,
   // C = block-transposed; L_R L_C S_C H_R H_C X_R X_C M_C Mb_R Mb_C Xb_R
   lsdm::DevBuf b16[11];

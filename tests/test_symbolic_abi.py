@@ -250,17 +250,18 @@ def test_bench_refuses_more_than_one_gpu():
 
 def test_degenerate_systems():
     """One atom (open): every pattern holds its on-site block only, and each of
-    the chain's eight products has exactly one block triple in either mode;
-    zero atoms are refused."""
+    the chain's products has exactly one block triple (eight in the full
+    chain, seven in symmetric mode, where dE/dL's 6 HX term is a projection of
+    B1's HX); zero atoms are refused."""
     s1 = workloads.System(xyz=np.zeros((1, 3)), nfn=np.array([4], np.int32), lattice=None)
     g = lsdm.System.from_workload(s1)
     for R in (0.0, 5.0, 100.0):
         p = lsdm.Pattern(g, R)
         assert (p.n_blocks, p.n_values) == (1, 16)
         assert oracle.pattern(s1, R).nblocks == 1
-    for sym in (False, True):
+    for sym, n_adj in ((False, 5), (True, 4)):
         lnv = lsdm.LNV(g, 4.0, 5.0, 5.0, symmetric=sym)
-        assert lnv.info(False) == (3, 3 * 128.0) and lnv.info(True) == (8, 8 * 128.0)
+        assert lnv.info(False) == (3, 3 * 128.0) and lnv.info(True) == (3 + n_adj, (3 + n_adj) * 128.0)
     with pytest.raises(lsdm.LsdmError) as e:
         lsdm.System(np.zeros((0, 3)), np.zeros(0, np.int32))
     assert e.value.code == lsdm._lib.EINVAL
