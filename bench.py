@@ -76,17 +76,18 @@ def profile_mode(lnv, inp, prec, steps):
 
 
 def algorithmic_bytes(lnv, symmetric, op_bytes, out_bytes):
-    """Compulsory bytes of one step's eight products: every operand read once
+    """Compulsory bytes of one step's products: every operand read once
     (op_bytes per value) and every output written once (out_bytes per value;
     read too where the product accumulates), on the block layout's values; a
-    half-output product writes half of its output."""
+    half-output product writes half of its output.  In symmetric mode the
+    6 HX term is a projection of Y = HX, not a product, and is not counted."""
     n = {w: lnv.patterns[w].n_values for w in "SHLXM"}
     #        A    B    C    output share  accumulates
     prods = [("L", "S", "X", 1.0, False), ("X", "L", "M", 0.5 if symmetric else 1.0, False),
              ("X", "M", "H", 0.5 if symmetric else 1.0, False), ("X", "H", "M", 1.0, False),
              ("H", "M", "X", 1.0, False)]
     if symmetric:
-        prods += [("M", "X", "L", 0.5, False), ("H", "X", "L", 1.0, False), ("X", "S", "L", 1.0, True)]
+        prods += [("X", "M", "L", 0.5, False), ("X", "S", "L", 1.0, True)]
     else:
         prods += [("M", "L", "X", 1.0, True), ("X", "M", "L", 1.0, False), ("X", "S", "L", 1.0, True)]
     tot = 0.0
@@ -330,7 +331,7 @@ def main():
                    "triples_per_step": n_triples, "symbolic_s": round(t_sym, 2), "symmetric": symmetric,
                    "parallelism": "single GPU"},
         "modes": {m: {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()} for m, r in res.items()},
-        "roofline": dict({"kernel": f"{PRODUCT_KERNEL[args.prec]} (all 8 product launches of a step, HIP-event "
+        "roofline": dict({"kernel": f"{PRODUCT_KERNEL[args.prec]} (all product launches of a step, HIP-event "
                                     f"time; frac_step: the same work over the whole step; traffic in HBM bytes "
                                     f"per step)"}, **roof,
                          traffic=traffic_per_step(args.prec, cfg["name"]), per_product=per_product),
