@@ -422,7 +422,6 @@ __device__ __forceinline__ void gbatch(char* ring, int rec_cur, int op_cur, int 
                                        typename Mma16<T>::acc_t (&acc)[GJ], int lane, int wave, int a_off, int b_off,
                                        int abit) {
   typedef GLayout<T> L;
-  constexpr uint32_t COL = 1u | (1u << GJ) | (1u << (2 * GJ)) | (1u << (3 * GJ));
   const uint32_t base = lds_off(ring);
   static_assert(L::NPW == 3, "record field reads below");
   // the operand indices of this wavefront's pieces (records of batch q+DA)
@@ -448,6 +447,13 @@ __device__ __forceinline__ void gbatch(char* ring, int rec_cur, int op_cur, int 
       "s_waitcnt lgkmcnt(0)"
       : "=&v"(idx[0]), "=&v"(idx[1]), "=&v"(idx[2]), "=&v"(mr)
       : "v"(fa[0]), "v"(fa[1]), "v"(fa[2]), "v"(ma));
+  // lanes r < SB: the column quads of step r with any active slot of this
+  // wavefront (zero past the tile's end); lanes SB + r: row bits of step r
+  {
+    const uint32_t m = (uint32_t)mr;
+    const uint32_t cm = (m | (m >> GJ) | (m >> (2 * GJ)) | (m >> (3 * GJ))) & ((1u << GJ) - 1u);
+    mr = lane < L::SB ? (lane < nv ? (int)cm : 0) : mr;
+  }
   if (do_rec && wave == 0 && lane < L::RLANES) copy16(rec_src + 16 * lane, ring + rec_dst);
   if (do_ops) {
 #pragma unroll
@@ -462,19 +468,18 @@ __device__ __forceinline__ void gbatch(char* ring, int rec_cur, int op_cur, int 
     }
   }
   if (nv <= 0) return;
-#pragma unroll 1
+#pragma unroll
   for (int r = 0; r < L::SB; ++r) {
-    uint32_t mask = (uint32_t)__builtin_amdgcn_readlane(mr, r);
-    const uint32_t rows = (uint32_t)__builtin_amdgcn_readlane(mr, L::SB + r);
-    if (r >= nv) mask = 0u;
+    const uint32_t mask = (uint32_t)__builtin_amdgcn_readlane(mr, r);
     if (mask == 0u) continue;
+    const uint32_t rows = (uint32_t)__builtin_amdgcn_readlane(mr, L::SB + r);
     const uint32_t sA = base + op_cur + r * L::SV * (int)sizeof(T);
     T av, bv[GJ];
     lds_operands<T>(sA + a_off * (int)sizeof(T), sA + (L::AV + b_off) * (int)sizeof(T), av, bv);
     av = ((rows >> abit) & 1u) ? av : (T)0;
 #pragma unroll
     for (int j = 0; j < GJ; ++j)
-      if ((mask >> j) & COL) acc[j] = Mma16<T>::mma(av, bv[j], acc[j]);
+      if (mask & (1u << j)) acc[j] = Mma16<T>::mma(av, bv[j], acc[j]);
   }
 }
 
@@ -494,14 +499,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
   // LDS ring: NDS operand slots, then NRS record slots
   constexpr int DSLOT = SB * L::SV * (int)sizeof(T), RSLOT = SB * L::RW * 4;
   __shared__ __attribute__((aligned(16))) char ring[L::NDS * DSLOT + L::NRS * RSLOT];
-  auto dslot = [&](int x) { return (x % L::NDS) * DSLOT; };
-  auto rslot = [&](int x) { return L::NDS * DSLOT + (x % L::NRS) * RSLOT; };
+  auto dslot = [&](int x) { return x * DSLOT; };
+  auto rslot = [&](int x) { return L::NDS * DSLOT + x * RSLOT; };
   // output strips of each wavefront's 4 x GJ slots and their block masks
   __shared__ int cstr[GQ][4 * GJ];
   __shared__ uint8_t cmsk[GQ][4 * GJ];
 
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int arow = lane & 15, ai = arow >> 2, ar = arow & 3, kk = lane >> 4;
   const int a_off = (4 * wave + ai) * 16 + (TA ? (kk * 4 + ar) : (ar * 4 + kk));
   const int b_off = ((lane & 15) >> 2) * 16 + kk * 4 + (lane & 3);
@@ -541,6 +546,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     __syncthreads();
     // batch q runs the MFMAs of q (q >= 0) and copies operands q+DA and
     // records q+DA+1; batches -DA .. -1 only copy
+    // slot numbers of batch q: operands q % NDS, records q % NRS (running)
+    int ds0 = ((-DA) % L::NDS + L::NDS) % L::NDS, rs0 = ((-DA) % L::NRS + L::NRS) % L::NRS;
     for (int q = -DA; q < nb; ++q) {
       // this wavefront's copies of operands q and records q+DA are complete
       // (copies complete in issue order; the NPW copies of operands q+DA-1,
@@ -553,10 +560,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
       __builtin_amdgcn_s_waitcnt(WAIT_LGKM0);
       __builtin_amdgcn_s_barrier();
       asm volatile("" ::: "memory");
-      const int qc = q + 4 * L::NDS * L::NRS;   // non-negative for the slot arithmetic
-      gbatch<T, TA>(ring, rslot(qc), dslot(qc), rslot(qc + DA), dslot(qc + DA), rslot(qc + DA + 1),
+      const int ds1 = ds0 + DA >= L::NDS ? ds0 + DA - L::NDS : ds0 + DA;
+      const int rs1 = rs0 + DA >= L::NRS ? rs0 + DA - L::NRS : rs0 + DA;
+      const int rs2 = rs1 + 1 >= L::NRS ? rs1 + 1 - L::NRS : rs1 + 1;
+      gbatch<T, TA>(ring, rslot(rs0), dslot(ds0), rslot(rs1), dslot(ds1), rslot(rs2),
                     rec_src(q + DA + 1), q + DA + 1 < nb && q + DA + 1 > DA, q + DA < nb,
                     q >= 0 ? ns - SB * q : 0, A, B, na_blk, nb_str, acc, lane, wave, a_off, b_off, abit);
+      ds0 = ds0 + 1 == L::NDS ? 0 : ds0 + 1;
+      rs0 = rs0 + 1 == L::NRS ? 0 : rs0 + 1;
     }
     // epilogue: lane l, register v holds D[row][col]; f32 row = 4 (l/16) + v,
     // f64 row = 4 v + l/16; col = l % 16 (block t = col / 4, c = col % 4)
