@@ -163,7 +163,7 @@ def traffic_per_step(prec, workload):
     return round(sum(d["fetch_bytes"] + d["write_bytes"] for d in t["dispatches"]) / per_step, 0)
 
 
-def summarize_pmc(fetch_dir, write_dir, prec, out):
+def summarize_pmc(fetch_dir, write_dir, prec, out, steps=1):
     """Per-dispatch HBM bytes of the product kernels from two rocprofv3 --pmc
     runs (FETCH_SIZE, WRITE_SIZE in KiB), scaled by what the same counters read
     for the calibration copy (a torch copy of known size in the same run)."""
@@ -199,7 +199,7 @@ def summarize_pmc(fetch_dir, write_dir, prec, out):
             continue
         w = res["WRITE_SIZE"].get(did, [kn, 0.0])[1]
         prods[did] = (kn, v * f_fac * 1024, w * w_fac * 1024)
-    summ = {"kernel_hash": kernel_hash(), "prec": prec, "steps": 1, "fetch_scale": f_fac, "write_scale": w_fac,
+    summ = {"kernel_hash": kernel_hash(), "prec": prec, "steps": steps, "fetch_scale": f_fac, "write_scale": w_fac,
             "dispatches": [{"id": d, "kernel": k.split("(")[0], "fetch_bytes": f, "write_bytes": w}
                            for d, (k, f, w) in sorted(prods.items())]}
     with open(out, "w") as fh:
@@ -209,8 +209,10 @@ def summarize_pmc(fetch_dir, write_dir, prec, out):
 
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-pmc":
-        # --summarize-pmc FETCH_DIR WRITE_DIR PREC [OUT]: the counter runs of one step
-        summarize_pmc(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5] if len(sys.argv) > 5 else TRAFFIC_FILE)
+        # --summarize-pmc FETCH_DIR WRITE_DIR PREC [OUT [STEPS]]: the counter runs
+        # of STEPS chain steps (default 1)
+        summarize_pmc(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5] if len(sys.argv) > 5 else TRAFFIC_FILE,
+                      int(sys.argv[6]) if len(sys.argv) > 6 else 1)
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -269,7 +271,10 @@ def main():
     res = {}
     for m in modes:
         ms, E, G = time_mode(lnv, inp, m, args.steps, args.warmup)
-        res[m] = {"ms_per_step": ms, "E": E, "gflops": flops / (ms * 1e-3) / 1e9}
+        # useful flops of the products this mode launches (symmetric FP64
+        # forms E without P, so it runs one product fewer)
+        fl_m = sum(v[1] * v[2] for v in profile_mode(lnv, inp, m, 1).values()) if args.profile_steps > 0 else flops
+        res[m] = {"ms_per_step": ms, "E": E, "gflops": fl_m / (ms * 1e-3) / 1e9, "flop_per_step": fl_m}
         log(f"[bench] {m}: {ms:.3f} ms/step  {res[m]['gflops']:.1f} GFLOP/s  E = {E:.12f}")
     if "fp64" in res:
         for m in res:
@@ -311,7 +316,8 @@ def main():
         peak = PEAK_TFLOPS[args.prec]
         achieved = tot_fl / (tot_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "frac_step": round(flops / step_s / 1e12 / peak, 4)}
+                "frac": round(achieved / peak, 4),
+                "frac_step": round(prim["flop_per_step"] / step_s / 1e12 / peak, 4)}
 
     out = {
         "metric": "LNV energy+gradient step: useful block-sparse GFLOP/s (s/step in ms_per_step)",

@@ -207,7 +207,11 @@ int lsdm_lnv_energy(lsdm_lnv* lnv, int prec, const double* dL, const double* dS,
  * respect to each stored entry of L (blocks (i,j,n) and (j,i,-n) independent):
  *   6 (HLS + SLH) - 4 (HLSLS + SLHLS + SLSLH)
  * computed by the adjoint chain of the truncated products, in the same
- * precision mode as the forward products.  dGradL: device. */
+ * precision mode as the forward products.  dGradL: device.  In symmetric
+ * mode at FP64 the energy skips P: Tr(PH) = <X, HM> for symmetric M and H,
+ * and the adjoint forms -4 HM on X's pattern anyway, so E = 2 <3 M|_H, H> +
+ * <X, -4 HM>; the value equals that of lsdm_lnv_energy up to rounding (not
+ * bit for bit) and the call runs one product fewer. */
 int lsdm_lnv_energy_grad(lsdm_lnv* lnv, int prec, const double* dL, const double* dS, const double* dH,
                          double* dE, double* dGradL, void* stream);
 /* Exact line search (section 2: the ground state is the minimum of E over L;

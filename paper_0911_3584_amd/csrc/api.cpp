@@ -30,6 +30,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <type_traits>
 
 #include "kernels.h"
 #include "lsdm_internal.h"
@@ -312,7 +313,7 @@ static void lnv_build(lsdm_lnv* L) {
   ws(L->wXb, L->pX);
   ws(L->wLb, L->pL);
   if (h) ws(L->wV, L->pL);
-  L->wE.alloc(sizeof(double) * 2 * DOT_BLOCKS + 64);
+  L->wE.alloc(sizeof(double) * 4 * DOT_BLOCKS + 64);
 }
 
 // the chain's products in a fixed order: F1 F2 F3 B1 B2 B3 B4 B5
@@ -339,9 +340,14 @@ static void chain_product(lsdm_lnv* L, int w, const T* A, const T* B, T* C, doub
   L->ev_prod.push_back(w);
 }
 
+// defer_p (symmetric mode, an energy-and-gradient call): P is not formed.
+// Tr(PH) = Tr(XMH) = <X, HM> for symmetric M and H, and the adjoint forms
+// Xbar = -4 P_X(HM) on X's pattern anyway, so E = 2 <3 M|_H, H> + <X, Xbar>:
+// the forward pass leaves the partial sums of the first dot in wE and the
+// backward pass adds the second after B2 and writes E.
 template <class T>
 static void lnv_forward(lsdm_lnv* L, const double* dL, const double* dS, const double* dH, double* dK, double* dE,
-                        hipStream_t st) {
+                        hipStream_t st, bool defer_p = false) {
   T* wL = L->wL.as<T>();
   T* wS = L->wS.as<T>();
   T* wH = L->wH.as<T>();
@@ -362,6 +368,12 @@ static void lnv_forward(lsdm_lnv* L, const double* dL, const double* dS, const d
   chain_product<T>(L, 0, wL, wS, wX, 1.0, 0.0, st);     // X = LS
   chain_product<T>(L, 1, wX, wL, wM, 1.0, 0.0, st);     // M = XL
   if (L->sym) sym_fill<T>(L->pM, wM, st);
+  if (defer_p) {
+    kassembly<T>(L, wM, nullptr, wK, st);                                 // 3 M|_H
+    dot_parts(wK, wH64, L->pH->n_strips * 64, L->wE.as<double>(), st);    // <3 M|_H, H>
+    check_launch();
+    return;
+  }
   chain_product<T>(L, 2, wX, wM, wP, 1.0, 0.0, st);     // P = XM on H's range
   if (L->sym) sym_fill<T>(L->pH, wP, st);
   kassembly<T>(L, wM, wP, wK, st);                  // K = 3 M|_H - 2 P
@@ -370,8 +382,9 @@ static void lnv_forward(lsdm_lnv* L, const double* dL, const double* dS, const d
   check_launch();
 }
 
+// dE: non-null when the forward pass deferred P (the energy is completed here)
 template <class T>
-static void lnv_backward(lsdm_lnv* L, double* dG, hipStream_t st) {
+static void lnv_backward(lsdm_lnv* L, double* dG, hipStream_t st, double* dE = nullptr) {
   T* wL = L->wL.as<T>();
   T* wS = L->wS.as<T>();
   T* wH = L->wH.as<T>();
@@ -392,11 +405,18 @@ static void lnv_backward(lsdm_lnv* L, double* dG, hipStream_t st) {
     T* wY = wMb;                                         // Y = H X on M's range (Mbar's workspace)
     chain_product<T>(L, 3, wH, wX, wY, 1.0, 0.0, st);    // Y = H X
     chain_product<T>(L, 4, wH, wM, wXb, -4.0, 0.0, st);  // Xbar = -4 H M
+    if constexpr (std::is_same<T, double>::value) {
+      if (dE) {                                          // E = 2 <3 M|_H, H> + <X, Xbar>
+        dot_parts(wX, wXb, L->pX->n_strips * 64, L->wE.as<double>() + 2 * DOT_BLOCKS, st);
+        dot_final2(L->wE.as<double>(), 2.0, 1.0, dE, st);
+      }
+    }
     chain_product<T>(L, 5, wX, wY, wLb, -4.0, 0.0, st);  // Lbar = -4 X^T Y = -4 X^T H X (half)
     project_strips<T>(L->pL, L->d_l2y.as<i64>(), wY, wV, 6.0, st);   // V = 6 P_L(Y) = 6 H X on L
     chain_product<T>(L, 7, wXb, wS, wV, 1.0, 1.0, st);   // V += Xbar S = -4 H M S
-    add_sym<T>(L->pL, wV, wLb, st);                      // Lbar += V + V^T
-    sym_fill<T>(L->pL, wLb, st);
+    sym_grad_to_user<T>(L->pL, wLb, wV, dG, st);         // dE/dL = Lbar + V + V^T, both halves
+    check_launch();
+    return;
   }
   strip_to_user<T>(L->pL, wLb, dG, st);
   check_launch();
@@ -500,8 +520,9 @@ static void lnv_backward_bf16(lsdm_lnv* L, double* dG, hipStream_t st) {
     chain_product_bf16(L, 5, h(XC), h(MbC), wLb, -4.0, 0.0, st); // Lbar = -4 X^T Y (half)
     project_strips<float>(L->pL, L->d_l2y.as<i64>(), wY, wV, 6.0, st);                  // V = 6 P_L(Y)
     chain_product_bf16(L, 7, h(XbR), h(SC), wV, 1.0, 1.0, st);  // V += Xbar S
-    add_sym<float>(L->pL, wV, wLb, st);                           // Lbar += V + V^T
-    sym_fill<float>(L->pL, wLb, st);
+    sym_grad_to_user<float>(L->pL, wLb, wV, dG, st);              // dE/dL = Lbar + V + V^T
+    check_launch();
+    return;
   }
   strip_to_user<float>(L->pL, wLb, dG, st);
   check_launch();
@@ -586,8 +607,9 @@ static void lnv_backward_rc(lsdm_lnv* L, double* dG, hipStream_t st) {
     rc_step(L, 5, wX, r(RX), wMb, r(RMb), wLb, -4.0, 0.0, st); // Lbar = -4 X^T Y (half)
     project_strips<double>(L->pL, L->d_l2y.as<i64>(), wMb, wV, 6.0, st);   // V = 6 P_L(Y)
     rc_step(L, 7, wXb, r(RXb), wS, r(RS), wV, 1.0, 1.0, st);   // V += Xbar S
-    add_sym<double>(L->pL, wV, wLb, st);                         // Lbar += V + V^T
-    sym_fill<double>(L->pL, wLb, st);
+    sym_grad_to_user<double>(L->pL, wLb, wV, dG, st);            // dE/dL = Lbar + V + V^T
+    check_launch();
+    return;
   }
   strip_to_user<double>(L->pL, wLb, dG, st);
   check_launch();
@@ -1146,8 +1168,9 @@ int lsdm_lnv_energy_grad(lsdm_lnv* L, int prec, const double* dL, const double* 
     if (!L || !dL || !dS || !dH || !dE || !dG) LSDM_THROW(LSDM_EINVAL, "null argument");
     hipStream_t st = (hipStream_t)stream;
     if (prec == LSDM_FP64) {
-      lnv_forward<double>(L, dL, dS, dH, nullptr, dE, st);
-      lnv_backward<double>(L, dG, st);
+      // symmetric mode: E without P (the same value; see lnv_forward)
+      lnv_forward<double>(L, dL, dS, dH, nullptr, dE, st, L->sym);
+      lnv_backward<double>(L, dG, st, L->sym ? dE : nullptr);
     } else if (prec == LSDM_FP32) {
       lnv_forward<float>(L, dL, dS, dH, nullptr, dE, st);
       lnv_backward<float>(L, dG, st);

@@ -21,7 +21,8 @@ template <class T> void transpose_strips(const lsdm_pattern* p, const T* in, T* 
 // the strips of a symmetric result outside keep_strip, as transposes of their mirrors
 template <class T> void sym_fill(const lsdm_pattern* p, T* data, hipStream_t st);
 // out += v + v^T (strip layout, every block of p)
-template <class T> void add_sym(const lsdm_pattern* p, const T* v, T* out, hipStream_t st);
+// dE/dL of symmetric mode into the caller's layout: Lbar (kept half) + V + V^T
+template <class T> void sym_grad_to_user(const lsdm_pattern* p, const T* Lb, const T* V, double* user, hipStream_t st);
 // C = alpha P_C(op(A) B) + beta C in strip layout (B already transposed if the plan says so)
 template <class T> void product(const lsdm_plan* pl, const T* A, const T* B, T* C, double alpha, double beta, hipStream_t st);
 // symbolic pass on the GPU: steps of a plan (count pass fill = 0, fill pass fill = 1)
@@ -55,6 +56,9 @@ template <class T>
 void project_strips(const lsdm_pattern* out, const i64* map, const T* in, T* o, double scale, hipStream_t st);
 // out[0] = scale * sum a[i] b[i]; partial holds 2 * DOT_BLOCKS doubles
 void dot(const double* a, const double* b, i64 n, double scale, double* partial, double* out, hipStream_t st);
+// partial sums of <a, b> (DOT_BLOCKS pairs), and s1 <first set> + s2 <second set> at partial + 2 DOT_BLOCKS
+void dot_parts(const double* a, const double* b, i64 n, double* partial, hipStream_t st);
+void dot_final2(const double* partial, double s1, double s2, double* out, hipStream_t st);
 // out = a x + b y, n doubles
 void lincomb(double* out, const double* x, const double* y, double a, double b, i64 n, hipStream_t st);
 // out[hoff[b] + e] += a * x[xoff[b] + e] for e < size[b], b < nb (distinct target blocks)

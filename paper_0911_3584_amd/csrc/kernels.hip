@@ -74,18 +74,47 @@ __global__ void k_transpose_strips(const T* __restrict__ in, T* __restrict__ out
   }
 }
 
-// out += v + v^T in strip layout, every block of the pattern: block t of strip
-// s adds the transpose of v's block at value offset mirror[4s+t] (nothing when
-// the mirror is absent)
+// dE/dL of symmetric mode in the caller's layout, one thread per element of
+// every 4x4 sub-block: Lbar + V + V^T, where Lbar holds only the kept half (a
+// block of the dropped half is the transpose of its mirror, as the mirror
+// fill would make it; zero when the mirror is absent) and V is whole.  The
+// sums are formed in the order that adding V + V^T to the kept half and then
+// mirroring it forms them, so either route gives the same bits.
 template <class T>
-__global__ void k_add_sym(T* __restrict__ out, const T* __restrict__ v, const i64* __restrict__ mirror, i64 nstrips) {
-  for (i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x; g < nstrips * 64; g += (i64)gridDim.x * blockDim.x) {
-    const i64 s = g >> 6;
-    const int t = (int)((g >> 4) & 3), r = (int)((g >> 2) & 3), c = (int)(g & 3);
+__global__ void k_sym_grad_to_user(const T* __restrict__ Lb, const T* __restrict__ V, double* __restrict__ user,
+                                   const i64* __restrict__ su, const i64* __restrict__ ss,
+                                   const i32* __restrict__ sh, i64 nsub, const i64* __restrict__ mirror,
+                                   const i32* __restrict__ srow, const i32* __restrict__ squad,
+                                   const i32* __restrict__ simg) {
+  for (i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x; g < nsub * 16; g += (i64)gridDim.x * blockDim.x) {
+    const i64 sb = g >> 4;
+    const int e = (int)(g & 15), r = e >> 2, c = e & 3;
+    const int shape = sh[sb], rows = shape & 255, cols = (shape >> 8) & 255, stride = shape >> 16;
+    if (!(r < rows && c < cols)) continue;
+    const i64 so = ss[sb];                  // strip-layout offset of the block's (0, 0)
+    const i64 s = so >> 6;
+    const int t = (int)((so >> 4) & 3);
+    const i32 p = srow[s], q = squad[s], n = simg[s];
+    const bool dropped = !keep_strip(p, q, n) || (q == (p >> 2) && n == IMG0 && 4 * q + t < p);
     const i64 m = mirror[4 * s + t];
-    T x = v[g];
-    if (m >= 0) x += v[m + c * 4 + r];
-    out[g] += x;
+    T x;
+    if (!dropped) {
+      T w = V[so + r * 4 + c];
+      if (m >= 0) w += V[m + c * 4 + r];
+      x = Lb[so + r * 4 + c] + w;
+    } else if (m >= 0) {
+      // the mirror block (kept) after its own update, transposed
+      const i64 mo = m + c * 4 + r;
+      const i64 ms = m >> 6;
+      const int mt = (int)((m >> 4) & 3);
+      const i64 mm = mirror[4 * ms + mt];   // the mirror's mirror: this block
+      T w = V[mo];
+      if (mm >= 0) w += V[mm + r * 4 + c];
+      x = Lb[mo] + w;
+    } else {
+      x = (T)0;
+    }
+    user[su[sb] + (i64)r * stride + c] = (double)x;
   }
 }
 
@@ -933,7 +962,7 @@ __global__ void k_kassembly(const T* __restrict__ M, const T* __restrict__ P, do
     const bool in = (hmask[h] >> t) & 1;
     const i64 m = h2m[h];
     const double mv = m >= 0 ? (double)M[m * 64 + e] : 0.0;
-    K[g] = in ? 3.0 * mv - 2.0 * (double)P[g] : 0.0;
+    K[g] = in ? (P ? 3.0 * mv - 2.0 * (double)P[g] : 3.0 * mv) : 0.0;
   }
 }
 
@@ -1073,14 +1102,15 @@ template void transpose_strips<double>(const lsdm_pattern*, const double*, doubl
 template void transpose_strips<float>(const lsdm_pattern*, const float*, float*, hipStream_t);
 
 template <class T>
-void add_sym(const lsdm_pattern* p, const T* v, T* out, hipStream_t st) {
+void sym_grad_to_user(const lsdm_pattern* p, const T* Lb, const T* V, double* user, hipStream_t st) {
   ensure_maps(const_cast<lsdm_pattern*>(p));
-  if (p->n_strips == 0) return;
-  hipLaunchKernelGGL(k_add_sym<T>, dim3(grid_for(p->n_strips * 64)), dim3(256), 0, st, out, v,
-                     p->d_mirror.as<i64>(), p->n_strips);
+  if (p->n_sub == 0) return;
+  hipLaunchKernelGGL(k_sym_grad_to_user<T>, dim3(grid_for(p->n_sub * 16)), dim3(256), 0, st, Lb, V, user,
+                     p->d_sub_user.as<i64>(), p->d_sub_strip.as<i64>(), p->d_sub_shape.as<i32>(), p->n_sub,
+                     p->d_mirror.as<i64>(), p->d_srow.as<i32>(), p->d_squad.as<i32>(), p->d_simg.as<i32>());
 }
-template void add_sym<double>(const lsdm_pattern*, const double*, double*, hipStream_t);
-template void add_sym<float>(const lsdm_pattern*, const float*, float*, hipStream_t);
+template void sym_grad_to_user<double>(const lsdm_pattern*, const double*, const double*, double*, hipStream_t);
+template void sym_grad_to_user<float>(const lsdm_pattern*, const float*, const float*, double*, hipStream_t);
 
 template <class T>
 void sym_fill(const lsdm_pattern* p, T* data, hipStream_t st) {
@@ -1313,6 +1343,37 @@ void add_blocks(double* out, const double* x, const i64* xoff, const i64* hoff, 
   if (nb <= 0) return;
   const i64 grid = std::min<i64>((nb + 3) / 4, 4096);
   hipLaunchKernelGGL(k_add_blocks, dim3((unsigned)grid), dim3(256), 0, st, out, x, xoff, hoff, size, nb, a);
+}
+
+// E from two compensated dots: s1 <a1, b1> + s2 <a2, b2>, the partial sums of
+// each set merged in one pass (s1, s2 powers of two keep the merge exact)
+__global__ void __launch_bounds__(256) k_dot_final2(const double* __restrict__ partial, int np, double s1,
+                                                    double s2, double* __restrict__ out) {
+  __shared__ double ss[256], sc[256];
+  Comp acc{0.0, 0.0};
+  for (int i = threadIdx.x; i < np; i += 256) {
+    acc = comp_merge(acc, Comp{s1 * partial[2 * i], s1 * partial[2 * i + 1]});
+    acc = comp_merge(acc, Comp{s2 * partial[2 * (np + i)], s2 * partial[2 * (np + i) + 1]});
+  }
+  ss[threadIdx.x] = acc.s;
+  sc[threadIdx.x] = acc.c;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      Comp m = comp_merge(Comp{ss[threadIdx.x], sc[threadIdx.x]}, Comp{ss[threadIdx.x + w], sc[threadIdx.x + w]});
+      ss[threadIdx.x] = m.s;
+      sc[threadIdx.x] = m.c;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = ss[0] + sc[0];
+}
+
+void dot_parts(const double* a, const double* b, i64 n, double* partial, hipStream_t st) {
+  hipLaunchKernelGGL(k_dot_partial<double>, dim3(DOT_BLOCKS), dim3(256), 0, st, a, b, n, partial);
+}
+void dot_final2(const double* partial, double s1, double s2, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_dot_final2, dim3(1), dim3(256), 0, st, partial, DOT_BLOCKS, s1, s2, out);
 }
 
 void dot(const double* a, const double* b, i64 n, double scale, double* partial, double* out, hipStream_t st) {

@@ -165,7 +165,13 @@ def test_lnv_energy_grad_fp64(name, symmetric):
     assert abs(E.item() - ref["E"]) <= TOL64 * abs(ref["E"]), (E.item(), ref["E"])
     assert rel(K.cpu().numpy(), ref["K"].val) <= TOL64
     E2, G = lnv.energy_grad(T(v["L"]), T(v["S"]), T(v["H"]))
-    assert E2.item() == E.item()
+    if symmetric:
+        # the energy-and-gradient call forms E without P in symmetric FP64 mode
+        # (2 <3 M|_H, H> + <X, Xbar>, the same value): held to the oracle, not
+        # to the bits of the energy call
+        assert abs(E2.item() - ref["E"]) <= TOL64 * abs(ref["E"]), (E2.item(), ref["E"])
+    else:
+        assert E2.item() == E.item()
     assert rel(G.cpu().numpy(), G_ref.val) <= TOL64, rel(G.cpu().numpy(), G_ref.val)
 
 

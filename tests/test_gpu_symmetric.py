@@ -73,7 +73,13 @@ def test_chain_blockwise_nondecaying(name, symmetric):
     eK = blockwise_rel(K, ref["K"].val, pH)
     eG = blockwise_rel(G, Gref.val, pL)
     say(f"    E rel {eE:.2e}  K worst block {eK:.2e}  dE/dL worst block {eG:.2e}")
-    assert E2.item() == E.item()
+    if symmetric:
+        # the energy-and-gradient call forms E without P in symmetric FP64 mode
+        # (2 <3 M|_H, H> + <X, Xbar>, the same value): held to the oracle, not
+        # to the bits of the energy call
+        assert abs(E2.item() - ref["E"]) <= TOL64 * abs(ref["E"]), (E2.item(), ref["E"])
+    else:
+        assert E2.item() == E.item()
     assert eE <= TOL64 and eK <= TOL64 and eG <= TOL64, (eE, eK, eG)
     if symmetric:
         assert_mirrored(K, pH)
