@@ -296,6 +296,12 @@ static void lnv_build(lsdm_lnv* L) {
   // blocks of K are -2 P alone and carry no 6H into Mbar
   const std::vector<i64> h2m = strip_map(L->sys, L->pH, L->pM, nullptr);
   L->d_h2m.upload(h2m.data(), sizeof(i64) * h2m.size());
+  {   // M strips that K reads (the BF16 chain writes FP32 M only there)
+    std::vector<uint8_t> need((size_t)L->pM->n_strips, 0);
+    for (const i64 m : h2m)
+      if (m >= 0) need[(size_t)m] = 1;
+    L->d_mneed.upload(need.data(), need.size());
+  }
   if (h) {   // L strip -> M strip (Y's projection on L's range; M's range holds L's)
     const std::vector<i64> l2y = strip_map(L->sys, L->pL, L->pM, "L range exceeds the LSL range");
     L->d_l2y.upload(l2y.data(), sizeof(i64) * l2y.size());
@@ -374,8 +380,7 @@ static void lnv_forward(lsdm_lnv* L, const double* dL, const double* dS, const d
     check_launch();
     return;
   }
-  chain_product<T>(L, 2, wX, wM, wP, 1.0, 0.0, st);     // P = XM on H's range
-  if (L->sym) sym_fill<T>(L->pH, wP, st);
+  chain_product<T>(L, 2, wX, wM, wP, 1.0, 0.0, st);     // P = XM on H's range (kept half when symmetric)
   kassembly<T>(L, wM, wP, wK, st);                  // K = 3 M|_H - 2 P
   dot(wK, wH64, L->pH->n_strips * 64, 2.0, L->wE.as<double>(), dE, st);   // E = 2 <K, H>
   if (dK) strip_to_user<double>(L->pH, wK, dK, st);
@@ -441,9 +446,9 @@ static void bf16_workspaces(lsdm_lnv* L, hipStream_t st) {
 
 static void chain_product_bf16(lsdm_lnv* L, int w, const unsigned short* A, const unsigned short* B, float* C,
                                double alpha, double beta, hipStream_t st, unsigned short* outR = nullptr,
-                               unsigned short* outC = nullptr) {
+                               unsigned short* outC = nullptr, const uint8_t* cneed = nullptr) {
   if (!L->prof) {
-    product_bf16(chain_plan(L, w), A, B, C, alpha, beta, st, outR, outC);
+    product_bf16(chain_plan(L, w), A, B, C, alpha, beta, st, outR, outC, cneed);
     return;
   }
   while (L->ev_pool.size() < L->ev_used + 2) {
@@ -452,7 +457,7 @@ static void chain_product_bf16(lsdm_lnv* L, int w, const unsigned short* A, cons
     L->ev_pool.push_back(e);
   }
   HIP_CHECK(hipEventRecord(L->ev_pool[L->ev_used], st));
-  product_bf16(chain_plan(L, w), A, B, C, alpha, beta, st, outR, outC);
+  product_bf16(chain_plan(L, w), A, B, C, alpha, beta, st, outR, outC, cneed);
   HIP_CHECK(hipEventRecord(L->ev_pool[L->ev_used + 1], st));
   L->ev_used += 2;
   L->ev_prod.push_back(w);
@@ -480,14 +485,12 @@ static void lnv_forward_bf16(lsdm_lnv* L, const double* dL, const double* dS, co
   }
   // X = LS: only its bf16 copies are used later
   chain_product_bf16(L, 0, h(LR), h(SC), nullptr, 1.0, 0.0, st, h(XR), h(XC));
-  // M = XL: FP32 for K, block-transposed bf16 copy for the products
-  chain_product_bf16(L, 1, h(XR), h(LC), wM, 1.0, 0.0, st, nullptr, h(MC));
-  if (L->sym) {
-    sym_fill<float>(L->pM, wM, st);
-    sym_fill<u16>(L->pM, h(MC), st);                           // the mirror rule holds for transposed blocks too
-  }
+  // M = XL: FP32 only on the strips K reads (kept half when symmetric: K
+  // reads mirrors), and the block-transposed bf16 copy for the products,
+  // whose epilogue writes the dropped half of a symmetric M as well (the copy
+  // of a mirror block is the row-major copy of its kept block)
+  chain_product_bf16(L, 1, h(XR), h(LC), wM, 1.0, 0.0, st, nullptr, h(MC), L->d_mneed.as<uint8_t>());
   chain_product_bf16(L, 2, h(XR), h(MC), wP, 1.0, 0.0, st);    // P = XM on H's range
-  if (L->sym) sym_fill<float>(L->pH, wP, st);
   kassembly<float>(L, wM, wP, wK, st);
   dot(wK, wH64, L->pH->n_strips * 64, 2.0, L->wE.as<double>(), dE, st);
   if (dK) strip_to_user<double>(L->pH, wK, dK, st);
@@ -574,7 +577,6 @@ static void lnv_forward_rc(lsdm_lnv* L, const double* dL, const double* dS, cons
   if (L->sym) sym_fill<double>(L->pM, wM, st);
   offsite_f32(L->pM, wM, r(RM), st);
   rc_step(L, 2, wX, r(RX), wM, r(RM), wP, 1.0, 0.0, st);       // P = XM on H's range
-  if (L->sym) sym_fill<double>(L->pH, wP, st);
   kassembly<double>(L, wM, wP, wK, st);
   dot(wK, wH, L->pH->n_strips * 64, 2.0, L->wE.as<double>(), dE, st);
   if (dK) strip_to_user<double>(L->pH, wK, dK, st);

@@ -43,13 +43,16 @@ void user_to_bf16(const lsdm_pattern* p, const double* user, unsigned short* out
                   hipStream_t st);
 // C (fp32) = alpha P_C(op(A) B) + beta C with bf16 operands (A: R copy, or C copy of X when transposed; B: C copy);
 // C may be null when only the bf16 copies of the result are wanted (outR, outC: nullable, written from the
-// FP32 result in the product's epilogue)
+// FP32 result in the product's epilogue); cneed (nullable, a byte per C strip) limits the FP32 writes to the
+// strips marked.  A half plan's outC also receives the copy's dropped half (mirrors of the kept blocks).
 void product_bf16(const lsdm_plan* pl, const unsigned short* A, const unsigned short* B, float* C, double alpha,
-                  double beta, hipStream_t st, unsigned short* outR = nullptr, unsigned short* outC = nullptr);
+                  double beta, hipStream_t st, unsigned short* outR = nullptr, unsigned short* outC = nullptr,
+                  const uint8_t* cneed = nullptr);
 template <class T> void kassembly(const lsdm_lnv* L, const T* M, const T* P, double* K, hipStream_t st);
 // K = 3 M|_out - 2 P on an output pattern: map[s] = M's strip with out's strip s key
 template <class T>
-void kassembly_on(const lsdm_pattern* out, const i64* map, const T* M, const T* P, double* K, hipStream_t st);
+void kassembly_on(const lsdm_pattern* out, const i64* map, const T* M, const T* P, double* K, hipStream_t st,
+                  const lsdm_pattern* Mpat = nullptr);
 template <class T> void scatter_h(const lsdm_lnv* L, const T* H, T* Mb, double scale, hipStream_t st);
 // o = scale * P_out(in) in strip layout: out's strip s from in's strip map[s], masked to out's blocks
 template <class T>

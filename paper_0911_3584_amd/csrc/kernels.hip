@@ -637,14 +637,40 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
 // ---------------------------------------------------------------------------
 typedef int i2v __attribute__((ext_vector_type(2)));
 
+// Exchange across the 4 lanes of a quad (DPP quad_perm): lane c gets v of
+// lane perm[c].
+template <int CTRL>
+__device__ __forceinline__ float quad_perm(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+// 4x4 transpose held by the 4 lanes of a quad: on entry lane c (c = lane & 3)
+// holds column c (a[r] = M[r][c]), on exit row c (a[x] = M[c][x]).  Two
+// butterfly rounds: lanes c and c^2 swap the off-diagonal 2x2 halves, then
+// lanes c and c^1 swap the off-diagonal elements of each 2x2 block.  Every
+// lane of the quad must execute it.
+__device__ __forceinline__ void quad_transpose(float (&a)[4], int c) {
+  const bool h = (c & 2) != 0;
+  float s0 = h ? a[0] : a[2], s1 = h ? a[1] : a[3];
+  float r0 = quad_perm<0x4E>(s0), r1 = quad_perm<0x4E>(s1);    // lanes [2, 3, 0, 1]
+  if (h) { a[0] = r0; a[1] = r1; } else { a[2] = r0; a[3] = r1; }
+  const bool odd = (c & 1) != 0;
+  s0 = odd ? a[0] : a[1];
+  s1 = odd ? a[2] : a[3];
+  r0 = quad_perm<0xB1>(s0);                                     // lanes [1, 0, 3, 2]
+  r1 = quad_perm<0xB1>(s1);
+  if (odd) { a[0] = r0; a[2] = r1; } else { a[1] = r0; a[3] = r1; }
+}
+
 template <bool TA>
-__global__ void __launch_bounds__(256) k_gprod_bf16(const GTile* __restrict__ tiles, i64 ntiles,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_gprod_bf16(const GTile* __restrict__ tiles, i64 ntiles,
                                                     const GStep* __restrict__ steps,
                                                     const unsigned short* __restrict__ A,
                                                     const unsigned short* __restrict__ B, float* __restrict__ C,
                                                     unsigned short* __restrict__ outR, unsigned short* __restrict__ outC,
                                                     const uint8_t* __restrict__ cmask, float alpha, float beta,
-                                                    unsigned long long* __restrict__ queue) {
+                                                    unsigned long long* __restrict__ queue, const i64* __restrict__ cmir,
+                                                    const i32* __restrict__ csquad, const i32* __restrict__ csimg,
+                                                    const uint8_t* __restrict__ cneed) {
   constexpr int SB = 8;                 // steps per batch: one MFMA of K = 32 per column quad
   constexpr int AV = GROWS * 16;
   constexpr int BV = GJ * 64;
@@ -661,6 +687,10 @@ __global__ void __launch_bounds__(256) k_gprod_bf16(const GTile* __restrict__ ti
   __shared__ __attribute__((aligned(16))) int rbuf[3][SB * RW];
   __shared__ int cstr[GQ][4 * GJ];
   __shared__ uint8_t cmsk[GQ][4 * GJ];
+  // symmetric results: mirror block (value offset / 16) of each slot's 4
+  // blocks and which of block / mirror the epilogue writes (bits tb, 4 + tb)
+  __shared__ int4 cmb[GQ][4 * GJ];
+  __shared__ uint8_t cwr[GQ][4 * GJ];
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -744,6 +774,27 @@ __global__ void __launch_bounds__(256) k_gprod_bf16(const GTile* __restrict__ ti
       cstr[wave][lane] = my_cs;
       cmsk[wave][lane] = (uint8_t)(my_cs >= 0 ? cmask[my_cs] : 0);
     }
+    // mirror writes of this wavefront's slots (lane = slot GJ i + jq, row i of
+    // its quad), loaded now and kept in registers until the epilogue.  In the
+    // row's own quad at image 0 the blocks below the diagonal are written only
+    // as mirrors of the blocks above it.
+    int4 my_mb = int4{-1, -1, -1, -1};
+    int my_wr = 0x0f;
+    if (cmir && lane < 4 * GJ && my_cs >= 0) {
+      const i32 prow = GROWS * tp->group + 4 * wave + lane / GJ, cq = csquad[my_cs];
+      const bool own = cq == (prow >> 2) && csimg[my_cs] == IMG0;
+      int mb[4];
+      my_wr = 0;
+#pragma unroll
+      for (int tb = 0; tb < 4; ++tb) {
+        const i32 qcol = 4 * cq + tb;
+        const bool self = !(own && qcol < prow), mir = !(own && qcol <= prow);
+        const i64 m = mir ? cmir[4 * (i64)my_cs + tb] : -1;
+        mb[tb] = m >= 0 ? (int)(m >> 4) : -1;
+        my_wr |= (self ? 1 : 0) << tb;
+      }
+      my_mb = int4{mb[0], mb[1], mb[2], mb[3]};
+    }
     for (int q = 0; q < nb; ++q) {
       __syncthreads();
       const bool more_r = q + 2 < nb, more_d = q + 1 < nb;
@@ -794,23 +845,55 @@ __global__ void __launch_bounds__(256) k_gprod_bf16(const GTile* __restrict__ ti
       if (more_r) store_records(rn, (q + 2) % 3);
     }
     {
-      const int col = lane & 15, tb = col >> 2, cc = col & 3;
+      // lane l holds rows 0..3 of column cc of block tb in row i of its row
+      // quad; the bf16 copies are written 8 bytes per lane: the
+      // block-transposed copy (outC) takes the lane's column as is, the
+      // row-major copy (outR) and the mirror block of a symmetric result take
+      // row cc after a transpose across the lane's quad
+      const int col = lane & 15, tb = col >> 2, cc = col & 3, i = lane >> 4;
+      if (cmir) {
+        if (lane < 4 * GJ) {
+          cmb[wave][lane] = my_mb;
+          cwr[wave][lane] = (uint8_t)my_wr;
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
 #pragma unroll
-      for (int j = 0; j < GJ; ++j)
+      for (int j = 0; j < GJ; ++j) {
+        const int cs = cstr[wave][GJ * i + j];
+        const bool in = cs >= 0 && ((cmsk[wave][GJ * i + j] >> tb) & 1);
+        float o[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int i = lane >> 4, rr = v;
-          const int2 ci = int2{cstr[wave][GJ * i + j], (int)cmsk[wave][GJ * i + j]};
-          if (ci.x < 0) continue;
-          const i64 idx = (i64)ci.x * 64 + tb * 16 + rr * 4 + cc;
-          float o = ((ci.y >> tb) & 1) ? alpha * acc[j][v] : 0.f;
-          if (beta != 0.f) o += beta * C[idx];
-          if (C) C[idx] = o;
-          // bf16 operand copies for later products, rounded from the FP32
-          // result as a separate conversion pass would
-          if (outR) outR[idx] = bf16_rne(o);
-          if (outC) outC[(i64)ci.x * 64 + tb * 16 + cc * 4 + rr] = bf16_rne(o);
+          o[v] = in ? alpha * acc[j][v] : 0.f;
+          if (cs >= 0) {
+            const i64 idx = (i64)cs * 64 + tb * 16 + v * 4 + cc;
+            if (beta != 0.f) o[v] += beta * C[idx];
+            if (C && (!cneed || cneed[cs])) C[idx] = o[v];
+          }
         }
+        // a symmetric result (cmir non-null, half plan) also gets its dropped
+        // half: the block-transposed copy of the mirror block (q, p, -n) is the
+        // row-major copy of this block (slot tables above)
+        bool self = true;
+        i64 mirror = -1;
+        if (cmir && cs >= 0) {
+          const int4 mbv = cmb[wave][GJ * i + j];
+          self = (cwr[wave][GJ * i + j] >> tb) & 1;
+          const int mbi = tb == 0 ? mbv.x : tb == 1 ? mbv.y : tb == 2 ? mbv.z : mbv.w;
+          mirror = mbi >= 0 ? (i64)mbi * 16 : -1;
+        }
+        // rounded from the FP32 result as a separate conversion pass would
+        if (outC && cs >= 0 && self)
+          *reinterpret_cast<ushort4*>(outC + (i64)cs * 64 + tb * 16 + cc * 4) =
+              make_ushort4(bf16_rne(o[0]), bf16_rne(o[1]), bf16_rne(o[2]), bf16_rne(o[3]));
+        if (outR || cmir) {
+          quad_transpose(o, cc);             // o[x] = row cc, column x
+          const ushort4 row = make_ushort4(bf16_rne(o[0]), bf16_rne(o[1]), bf16_rne(o[2]), bf16_rne(o[3]));
+          if (outR && cs >= 0) *reinterpret_cast<ushort4*>(outR + (i64)cs * 64 + tb * 16 + cc * 4) = row;
+          if (mirror >= 0) *reinterpret_cast<ushort4*>(outC + mirror + cc * 4) = row;
+        }
+      }
     }
     __syncthreads();
   }
@@ -951,18 +1034,44 @@ __global__ void k_rc_apply(const uint8_t* __restrict__ cmask, const i32* __restr
 
 // ---------------------------------------------------------------------------
 // K = 3 M|_H - 2 P on H's strips (FP64), masked to H's pattern; an H strip
-// outside M's pattern (h2m = -1: beyond the range of LSL) takes M as zero
+// outside M's pattern (h2m = -1: beyond the range of LSL) takes M as zero.
+// Symmetric results (sym non-null) may hold only their kept half: a block of
+// the dropped half (same rule for an H strip and the M strip with the same
+// row, quad and image) reads the transpose of its mirror in M and in P, the
+// values a mirror fill would have copied there (zero when absent).
 // ---------------------------------------------------------------------------
+struct KSym {
+  const i64* mir_m;    // M's mirror map
+  const i64* mir_h;    // H's mirror map (P lives on H's pattern)
+  const i32* srow;     // H's strips: row, column quad, image
+  const i32* squad;
+  const i32* simg;
+};
+
 template <class T>
 __global__ void k_kassembly(const T* __restrict__ M, const T* __restrict__ P, double* __restrict__ K,
-                            const i64* __restrict__ h2m, const uint8_t* __restrict__ hmask, i64 nh) {
+                            const i64* __restrict__ h2m, const uint8_t* __restrict__ hmask, i64 nh, KSym sym) {
   for (i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x; g < nh * 64; g += (i64)gridDim.x * blockDim.x) {
     const i64 h = g >> 6;
-    const int e = (int)(g & 63), t = e >> 4;
+    const int e = (int)(g & 63), t = e >> 4, r = (e >> 2) & 3, c = e & 3;
     const bool in = (hmask[h] >> t) & 1;
     const i64 m = h2m[h];
-    const double mv = m >= 0 ? (double)M[m * 64 + e] : 0.0;
-    K[g] = in ? (P ? 3.0 * mv - 2.0 * (double)P[g] : 3.0 * mv) : 0.0;
+    bool dropped = false;
+    if (sym.srow) {
+      const i32 p = sym.srow[h], q = sym.squad[h], n = sym.simg[h];
+      dropped = !keep_strip(p, q, n) || (q == (p >> 2) && n == IMG0 && 4 * q + t < p);
+    }
+    double mv = 0.0, pv = 0.0;
+    if (!dropped) {
+      if (m >= 0) mv = (double)M[m * 64 + e];
+      if (P) pv = (double)P[g];
+    } else {
+      const i64 mm = m >= 0 ? sym.mir_m[4 * m + t] : -1;
+      const i64 mh = sym.mir_h[4 * h + t];
+      if (mm >= 0) mv = (double)M[mm + c * 4 + r];
+      if (P && mh >= 0) pv = (double)P[mh + c * 4 + r];
+    }
+    K[g] = in ? (P ? 3.0 * mv - 2.0 * pv : 3.0 * mv) : 0.0;
   }
 }
 
@@ -1264,7 +1373,7 @@ void user_to_bf16(const lsdm_pattern* p, const double* user, unsigned short* out
 }
 
 void product_bf16(const lsdm_plan* pl, const unsigned short* A, const unsigned short* B, float* C, double alpha,
-                  double beta, hipStream_t st, unsigned short* outR, unsigned short* outC) {
+                  double beta, hipStream_t st, unsigned short* outR, unsigned short* outC, const uint8_t* cneed) {
   if (pl->n_gtiles == 0) return;
   const GTile* Tl = pl->d_gtiles.as<GTile>();
   const GStep* S = pl->d_gsteps.as<GStep>();
@@ -1272,27 +1381,46 @@ void product_bf16(const lsdm_plan* pl, const unsigned short* A, const unsigned s
   const dim3 b(256);
   unsigned long long* q = pl->d_queue.as<unsigned long long>();
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, q, 8);
+  // half plans write the mirrors of their block-transposed copy
+  const i64* cmir = nullptr;
+  if (pl->half && outC) {
+    ensure_maps(const_cast<lsdm_pattern*>(pl->C));
+    cmir = pl->C->d_mirror.as<i64>();
+  }
+  const i32* csq = pl->C->d_squad.as<i32>();
+  const i32* csi = pl->C->d_simg.as<i32>();
   if (pl->transA)
     hipLaunchKernelGGL((k_gprod_bf16<true>), dim3(gproduct_grid(k_gprod_bf16<true>, pl->n_gtiles)), b, 0, st, Tl,
-                       pl->n_gtiles, S, A, B, C, outR, outC, cm, (float)alpha, (float)beta, q);
+                       pl->n_gtiles, S, A, B, C, outR, outC, cm, (float)alpha, (float)beta, q, cmir, csq, csi, cneed);
   else
     hipLaunchKernelGGL((k_gprod_bf16<false>), dim3(gproduct_grid(k_gprod_bf16<false>, pl->n_gtiles)), b, 0, st, Tl,
-                       pl->n_gtiles, S, A, B, C, outR, outC, cm, (float)alpha, (float)beta, q);
+                       pl->n_gtiles, S, A, B, C, outR, outC, cm, (float)alpha, (float)beta, q, cmir, csq, csi, cneed);
 }
 
 template <class T>
-void kassembly_on(const lsdm_pattern* out, const i64* map, const T* M, const T* P, double* K, hipStream_t st) {
+void kassembly_on(const lsdm_pattern* out, const i64* map, const T* M, const T* P, double* K, hipStream_t st,
+                  const lsdm_pattern* Mpat) {
   const i64 n = out->n_strips;
   if (n == 0) return;
+  KSym sym{nullptr, nullptr, nullptr, nullptr, nullptr};
+  if (Mpat) {
+    ensure_maps(const_cast<lsdm_pattern*>(out));
+    ensure_maps(const_cast<lsdm_pattern*>(Mpat));
+    sym = KSym{Mpat->d_mirror.as<i64>(), out->d_mirror.as<i64>(), out->d_srow.as<i32>(), out->d_squad.as<i32>(),
+               out->d_simg.as<i32>()};
+  }
   hipLaunchKernelGGL(k_kassembly<T>, dim3(grid_for(n * 64)), dim3(256), 0, st, M, P, K, map,
-                     out->d_smask.as<uint8_t>(), n);
+                     out->d_smask.as<uint8_t>(), n, sym);
 }
-template void kassembly_on<double>(const lsdm_pattern*, const i64*, const double*, const double*, double*, hipStream_t);
-template void kassembly_on<float>(const lsdm_pattern*, const i64*, const float*, const float*, double*, hipStream_t);
+template void kassembly_on<double>(const lsdm_pattern*, const i64*, const double*, const double*, double*, hipStream_t,
+                                   const lsdm_pattern*);
+template void kassembly_on<float>(const lsdm_pattern*, const i64*, const float*, const float*, double*, hipStream_t,
+                                  const lsdm_pattern*);
 
+// in symmetric mode M and P may hold only their kept halves (see k_kassembly)
 template <class T>
 void kassembly(const lsdm_lnv* L, const T* M, const T* P, double* K, hipStream_t st) {
-  kassembly_on<T>(L->pH, L->d_h2m.as<i64>(), M, P, K, st);
+  kassembly_on<T>(L->pH, L->d_h2m.as<i64>(), M, P, K, st, L->sym ? L->pM : nullptr);
 }
 template void kassembly<double>(const lsdm_lnv*, const double*, const double*, double*, hipStream_t);
 template void kassembly<float>(const lsdm_lnv*, const float*, const float*, double*, hipStream_t);
