@@ -305,6 +305,10 @@ static void lnv_build(lsdm_lnv* L) {
   if (h) {   // L strip -> M strip (Y's projection on L's range; M's range holds L's)
     const std::vector<i64> l2y = strip_map(L->sys, L->pL, L->pM, "L range exceeds the LSL range");
     L->d_l2y.upload(l2y.data(), sizeof(i64) * l2y.size());
+    std::vector<uint8_t> need((size_t)L->pM->n_strips, 0);   // M strips the projection reads
+    for (const i64 m : l2y)
+      if (m >= 0) need[(size_t)m] = 1;
+    L->d_yneed.upload(need.data(), need.size());
   }
   auto ws = [](DevBuf& b, const lsdm_pattern* p) { b.alloc(strip_bytes(p, sizeof(double))); };
   ws(L->wL, L->pL);
@@ -329,9 +333,10 @@ static lsdm_plan* chain_plan(const lsdm_lnv* L, int w) {
 }
 
 template <class T>
-static void chain_product(lsdm_lnv* L, int w, const T* A, const T* B, T* C, double alpha, double beta, hipStream_t st) {
+static void chain_product(lsdm_lnv* L, int w, const T* A, const T* B, T* C, double alpha, double beta, hipStream_t st,
+                          const T* Cin = nullptr, const i64* cmap = nullptr) {
   if (!L->prof) {
-    product<T>(chain_plan(L, w), A, B, C, alpha, beta, st);
+    product<T>(chain_plan(L, w), A, B, C, alpha, beta, st, Cin, cmap);
     return;
   }
   while (L->ev_pool.size() < L->ev_used + 2) {
@@ -340,7 +345,7 @@ static void chain_product(lsdm_lnv* L, int w, const T* A, const T* B, T* C, doub
     L->ev_pool.push_back(e);
   }
   HIP_CHECK(hipEventRecord(L->ev_pool[L->ev_used], st));
-  product<T>(chain_plan(L, w), A, B, C, alpha, beta, st);
+  product<T>(chain_plan(L, w), A, B, C, alpha, beta, st, Cin, cmap);
   HIP_CHECK(hipEventRecord(L->ev_pool[L->ev_used + 1], st));
   L->ev_used += 2;
   L->ev_prod.push_back(w);
@@ -417,8 +422,8 @@ static void lnv_backward(lsdm_lnv* L, double* dG, hipStream_t st, double* dE = n
       }
     }
     chain_product<T>(L, 5, wX, wY, wLb, -4.0, 0.0, st);  // Lbar = -4 X^T Y = -4 X^T H X (half)
-    project_strips<T>(L->pL, L->d_l2y.as<i64>(), wY, wV, 6.0, st);   // V = 6 P_L(Y) = 6 H X on L
-    chain_product<T>(L, 7, wXb, wS, wV, 1.0, 1.0, st);   // V += Xbar S = -4 H M S
+    // V = Xbar S + 6 P_L(Y) = -4 HMS + 6 HX on L: the projection of Y is B5's beta term
+    chain_product<T>(L, 7, wXb, wS, wV, 1.0, 6.0, st, wY, L->d_l2y.as<i64>());
     sym_grad_to_user<T>(L->pL, wLb, wV, dG, st);         // dE/dL = Lbar + V + V^T, both halves
     check_launch();
     return;
@@ -446,9 +451,10 @@ static void bf16_workspaces(lsdm_lnv* L, hipStream_t st) {
 
 static void chain_product_bf16(lsdm_lnv* L, int w, const unsigned short* A, const unsigned short* B, float* C,
                                double alpha, double beta, hipStream_t st, unsigned short* outR = nullptr,
-                               unsigned short* outC = nullptr, const uint8_t* cneed = nullptr) {
+                               unsigned short* outC = nullptr, const uint8_t* cneed = nullptr,
+                               const float* Cin = nullptr, const i64* cmap = nullptr) {
   if (!L->prof) {
-    product_bf16(chain_plan(L, w), A, B, C, alpha, beta, st, outR, outC, cneed);
+    product_bf16(chain_plan(L, w), A, B, C, alpha, beta, st, outR, outC, cneed, Cin, cmap);
     return;
   }
   while (L->ev_pool.size() < L->ev_used + 2) {
@@ -457,7 +463,7 @@ static void chain_product_bf16(lsdm_lnv* L, int w, const unsigned short* A, cons
     L->ev_pool.push_back(e);
   }
   HIP_CHECK(hipEventRecord(L->ev_pool[L->ev_used], st));
-  product_bf16(chain_plan(L, w), A, B, C, alpha, beta, st, outR, outC, cneed);
+  product_bf16(chain_plan(L, w), A, B, C, alpha, beta, st, outR, outC, cneed, Cin, cmap);
   HIP_CHECK(hipEventRecord(L->ev_pool[L->ev_used + 1], st));
   L->ev_used += 2;
   L->ev_prod.push_back(w);
@@ -518,11 +524,12 @@ static void lnv_backward_bf16(lsdm_lnv* L, double* dG, hipStream_t st) {
     float* wY = wMb;
     // Y = H X: FP32 for its projection, block-transposed bf16 copy as the
     // B operand of X^T Y (in Mbar's bf16 slot); Xbar is an operand only
-    chain_product_bf16(L, 3, h(HR), h(XC), wY, 1.0, 0.0, st, nullptr, h(MbC));         // Y = H X
+    chain_product_bf16(L, 3, h(HR), h(XC), wY, 1.0, 0.0, st, nullptr, h(MbC),          // Y = H X (FP32 only
+                       L->d_yneed.as<uint8_t>());                                       // on L's strips)
     chain_product_bf16(L, 4, h(HR), h(MC), nullptr, -4.0, 0.0, st, h(XbR), nullptr);   // Xbar = Pbar M
     chain_product_bf16(L, 5, h(XC), h(MbC), wLb, -4.0, 0.0, st); // Lbar = -4 X^T Y (half)
-    project_strips<float>(L->pL, L->d_l2y.as<i64>(), wY, wV, 6.0, st);                  // V = 6 P_L(Y)
-    chain_product_bf16(L, 7, h(XbR), h(SC), wV, 1.0, 1.0, st);  // V += Xbar S
+    chain_product_bf16(L, 7, h(XbR), h(SC), wV, 1.0, 6.0, st, nullptr, nullptr, nullptr,   // V = Xbar S
+                       wY, L->d_l2y.as<i64>());                                               //   + 6 P_L(Y)
     sym_grad_to_user<float>(L->pL, wLb, wV, dG, st);              // dE/dL = Lbar + V + V^T
     check_launch();
     return;

@@ -24,7 +24,11 @@ template <class T> void sym_fill(const lsdm_pattern* p, T* data, hipStream_t st)
 // dE/dL of symmetric mode into the caller's layout: Lbar (kept half) + V + V^T
 template <class T> void sym_grad_to_user(const lsdm_pattern* p, const T* Lb, const T* V, double* user, hipStream_t st);
 // C = alpha P_C(op(A) B) + beta C in strip layout (B already transposed if the plan says so)
-template <class T> void product(const lsdm_plan* pl, const T* A, const T* B, T* C, double alpha, double beta, hipStream_t st);
+// C = alpha P_C(op(A) B) + beta C; with cmap (C strip -> Cin strip, nullable) the beta term is
+// beta Cin on the mapped strips, masked to C's blocks, instead of beta C
+template <class T>
+void product(const lsdm_plan* pl, const T* A, const T* B, T* C, double alpha, double beta, hipStream_t st,
+             const T* Cin = nullptr, const i64* cmap = nullptr);
 // symbolic pass on the GPU: steps of a plan (count pass fill = 0, fill pass fill = 1)
 void plan_gsteps(const GTile* tiles, i64 ntiles, const GKEnt* kent, const i64* kbeg, const PlanView& v, int fill,
                  i32* counts, GStep* steps, unsigned long long* work);
@@ -47,7 +51,7 @@ void user_to_bf16(const lsdm_pattern* p, const double* user, unsigned short* out
 // strips marked.  A half plan's outC also receives the copy's dropped half (mirrors of the kept blocks).
 void product_bf16(const lsdm_plan* pl, const unsigned short* A, const unsigned short* B, float* C, double alpha,
                   double beta, hipStream_t st, unsigned short* outR = nullptr, unsigned short* outC = nullptr,
-                  const uint8_t* cneed = nullptr);
+                  const uint8_t* cneed = nullptr, const float* Cin = nullptr, const i64* cmap = nullptr);
 template <class T> void kassembly(const lsdm_lnv* L, const T* M, const T* P, double* K, hipStream_t st);
 // K = 3 M|_out - 2 P on an output pattern: map[s] = M's strip with out's strip s key
 template <class T>

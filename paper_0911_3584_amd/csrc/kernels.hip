@@ -520,7 +520,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
                                                const GStep* __restrict__ steps, const T* __restrict__ A,
                                                const T* __restrict__ B, T* __restrict__ C,
                                                const uint8_t* __restrict__ cmask, T alpha, T beta, int na_blk,
-                                               int nb_str, unsigned long long* __restrict__ queue) {
+                                               int nb_str, unsigned long long* __restrict__ queue,
+                                               const T* __restrict__ Cin, const i64* __restrict__ cmap) {
   typedef typename Mma16<T>::acc_t acc_t;
   typedef GLayout<T> L;
   constexpr bool F64 = sizeof(T) == 8;
@@ -602,8 +603,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     // f64 row = 4 v + l/16; col = l % 16 (block t = col / 4, c = col % 4)
     {
       const int col = lane & 15, tb = col >> 2, cc = col & 3;
+      // the beta term may come from another pattern's strips (cmap: C strip
+      // -> Cin strip), masked to C's blocks; a column quad's map entries are
+      // read together before its stores
 #pragma unroll
-      for (int j = 0; j < GJ; ++j)
+      for (int j = 0; j < GJ; ++j) {
+        int mv[4] = {-1, -1, -1, -1};
+        if (cmap) {
+#pragma unroll
+          for (int v = 0; v < (F64 ? 4 : 1); ++v) {
+            const int cs = cstr[wave][GJ * (F64 ? v : (lane >> 4)) + j];
+            mv[v] = cs >= 0 ? (int)cmap[cs] : -1;
+          }
+          if (!F64) mv[1] = mv[2] = mv[3] = mv[0];
+        }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int i = F64 ? v : (lane >> 4);
@@ -611,10 +624,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
           const int2 ci = int2{cstr[wave][GJ * i + j], (int)cmsk[wave][GJ * i + j]};
           if (ci.x < 0) continue;
           const i64 idx = (i64)ci.x * 64 + tb * 16 + rr * 4 + cc;
-          T o = ((ci.y >> tb) & 1) ? alpha * acc[j][v] : (T)0;
-          if (beta != (T)0) o += beta * C[idx];
+          const bool in = (ci.y >> tb) & 1;
+          T o = in ? alpha * acc[j][v] : (T)0;
+          if (cmap) {
+            // rounded as a separate scaled copy of Cin would be (no fused
+            // multiply-add), so the result does not depend on the route
+#pragma clang fp contract(off)
+            if (in) o += beta * Cin[(i64)mv[v] * 64 + (idx & 63)];
+          } else if (beta != (T)0) {
+            o += beta * C[idx];
+          }
           C[idx] = o;
         }
+      }
     }
     // the next tile's prologue rewrites record slots and the slot table
     __builtin_amdgcn_s_waitcnt(0);
@@ -670,7 +692,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
                                                     const uint8_t* __restrict__ cmask, float alpha, float beta,
                                                     unsigned long long* __restrict__ queue, const i64* __restrict__ cmir,
                                                     const i32* __restrict__ csquad, const i32* __restrict__ csimg,
-                                                    const uint8_t* __restrict__ cneed) {
+                                                    const uint8_t* __restrict__ cneed, const float* __restrict__ Cin,
+                                                    const i64* __restrict__ cmap) {
   constexpr int SB = 8;                 // steps per batch: one MFMA of K = 32 per column quad
   constexpr int AV = GROWS * 16;
   constexpr int BV = GJ * 64;
@@ -691,6 +714,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   // blocks and which of block / mirror the epilogue writes (bits tb, 4 + tb)
   __shared__ int4 cmb[GQ][4 * GJ];
   __shared__ uint8_t cwr[GQ][4 * GJ];
+  __shared__ int cmp[GQ][4 * GJ];   // cmap of each slot's strip (-1: none)
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -763,16 +787,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
       {
         i2v d[NPW];
         load_operands(0, d);
-        const int mk = my_cs >= 0 ? (int)cmask[my_cs] : 0;
+        // block mask, and bit 4: the FP32 result is written on this strip
+        const int mk = my_cs >= 0 ? (int)cmask[my_cs] | ((!cneed || cneed[my_cs]) ? 16 : 0) : 0;
+        const int mp = (cmap && my_cs >= 0) ? (int)cmap[my_cs] : -1;
         store_operands(d, 0);
         if (lane < 4 * GJ) {
           cstr[wave][lane] = my_cs;
           cmsk[wave][lane] = (uint8_t)mk;
+          cmp[wave][lane] = mp;
         }
       }
     } else if (lane < 4 * GJ) {
       cstr[wave][lane] = my_cs;
-      cmsk[wave][lane] = (uint8_t)(my_cs >= 0 ? cmask[my_cs] : 0);
+      cmsk[wave][lane] = (uint8_t)(my_cs >= 0 ? (int)cmask[my_cs] | ((!cneed || cneed[my_cs]) ? 16 : 0) : 0);
+      cmp[wave][lane] = (cmap && my_cs >= 0) ? (int)cmap[my_cs] : -1;
     }
     // mirror writes of this wavefront's slots (lane = slot GJ i + jq, row i of
     // its quad), loaded now and kept in registers until the epilogue.  In the
@@ -868,8 +896,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
           o[v] = in ? alpha * acc[j][v] : 0.f;
           if (cs >= 0) {
             const i64 idx = (i64)cs * 64 + tb * 16 + v * 4 + cc;
-            if (beta != 0.f) o[v] += beta * C[idx];
-            if (C && (!cneed || cneed[cs])) C[idx] = o[v];
+            if (cmap) {   // the beta term from another pattern's strips (see k_gprod)
+#pragma clang fp contract(off)
+              if (in) o[v] += beta * Cin[(i64)cmp[wave][GJ * i + j] * 64 + (idx & 63)];
+            } else if (beta != 0.f) {
+              o[v] += beta * C[idx];
+            }
+            if (C && ((cmsk[wave][GJ * i + j] >> 4) & 1)) C[idx] = o[v];
           }
         }
         // a symmetric result (cmir non-null, half plan) also gets its dropped
@@ -1263,7 +1296,8 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
 }
 
 template <class T>
-void product(const lsdm_plan* pl, const T* A, const T* B, T* C, double alpha, double beta, hipStream_t st) {
+void product(const lsdm_plan* pl, const T* A, const T* B, T* C, double alpha, double beta, hipStream_t st,
+             const T* Cin, const i64* cmap) {
   if (pl->n_gtiles == 0) return;
   const uint8_t* cm = pl->C->d_smask.as<uint8_t>();
   const GTile* Tl = pl->d_gtiles.as<GTile>();
@@ -1275,13 +1309,15 @@ void product(const lsdm_plan* pl, const T* A, const T* B, T* C, double alpha, do
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, q, 8);
   if (pl->transA)
     hipLaunchKernelGGL((k_gprod<T, true>), dim3(gproduct_grid(k_gprod<T, true>, pl->n_gtiles)), b, 0, st, Tl,
-                       pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta, na, nbs, q);
+                       pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta, na, nbs, q, Cin, cmap);
   else
     hipLaunchKernelGGL((k_gprod<T, false>), dim3(gproduct_grid(k_gprod<T, false>, pl->n_gtiles)), b, 0, st, Tl,
-                       pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta, na, nbs, q);
+                       pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta, na, nbs, q, Cin, cmap);
 }
-template void product<double>(const lsdm_plan*, const double*, const double*, double*, double, double, hipStream_t);
-template void product<float>(const lsdm_plan*, const float*, const float*, float*, double, double, hipStream_t);
+template void product<double>(const lsdm_plan*, const double*, const double*, double*, double, double, hipStream_t,
+                              const double*, const i64*);
+template void product<float>(const lsdm_plan*, const float*, const float*, float*, double, double, hipStream_t,
+                             const float*, const i64*);
 
 
 void plan_gsteps(const GTile* tiles, i64 ntiles, const GKEnt* kent, const i64* kbeg, const PlanView& v, int fill,
@@ -1373,7 +1409,8 @@ void user_to_bf16(const lsdm_pattern* p, const double* user, unsigned short* out
 }
 
 void product_bf16(const lsdm_plan* pl, const unsigned short* A, const unsigned short* B, float* C, double alpha,
-                  double beta, hipStream_t st, unsigned short* outR, unsigned short* outC, const uint8_t* cneed) {
+                  double beta, hipStream_t st, unsigned short* outR, unsigned short* outC, const uint8_t* cneed,
+                  const float* Cin, const i64* cmap) {
   if (pl->n_gtiles == 0) return;
   const GTile* Tl = pl->d_gtiles.as<GTile>();
   const GStep* S = pl->d_gsteps.as<GStep>();
@@ -1391,10 +1428,10 @@ void product_bf16(const lsdm_plan* pl, const unsigned short* A, const unsigned s
   const i32* csi = pl->C->d_simg.as<i32>();
   if (pl->transA)
     hipLaunchKernelGGL((k_gprod_bf16<true>), dim3(gproduct_grid(k_gprod_bf16<true>, pl->n_gtiles)), b, 0, st, Tl,
-                       pl->n_gtiles, S, A, B, C, outR, outC, cm, (float)alpha, (float)beta, q, cmir, csq, csi, cneed);
+                       pl->n_gtiles, S, A, B, C, outR, outC, cm, (float)alpha, (float)beta, q, cmir, csq, csi, cneed, Cin, cmap);
   else
     hipLaunchKernelGGL((k_gprod_bf16<false>), dim3(gproduct_grid(k_gprod_bf16<false>, pl->n_gtiles)), b, 0, st, Tl,
-                       pl->n_gtiles, S, A, B, C, outR, outC, cm, (float)alpha, (float)beta, q, cmir, csq, csi, cneed);
+                       pl->n_gtiles, S, A, B, C, outR, outC, cm, (float)alpha, (float)beta, q, cmir, csq, csi, cneed, Cin, cmap);
 }
 
 template <class T>

@@ -230,6 +230,7 @@ struct lsdm_lnv {
   lsdm::DevBuf d_h2m;               // i64 per H strip: M strip index (-1: none)
   lsdm::DevBuf d_mneed;             // u8 per M strip: 1 when some H strip maps to it
   lsdm::DevBuf d_l2y;               // symmetric mode: i64 per L strip, the M strip of Y = HX to project
+  lsdm::DevBuf d_yneed;             // symmetric mode: u8 per M strip, 1 when an L strip maps to it
   // bf16 operand copies (allocated on first BF16 use): R = row-major blocks,
   // C = block-transposed; L_R L_C S_C H_R H_C X_R X_C M_C Mb_R Mb_C Xb_R
   lsdm::DevBuf b16[11];
