@@ -441,6 +441,30 @@ __device__ __forceinline__ void lds_operands<double>(uint32_t a, uint32_t b, dou
       : "v"(a), "v"(b));
 }
 
+// Exchange across the 4 lanes of a quad (DPP quad_perm): lane c gets v of
+// lane perm[c].
+template <int CTRL>
+__device__ __forceinline__ float quad_perm(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+// 4x4 transpose held by the 4 lanes of a quad: on entry lane c (c = lane & 3)
+// holds column c (a[r] = M[r][c]), on exit row c (a[x] = M[c][x]).  Two
+// butterfly rounds: lanes c and c^2 swap the off-diagonal 2x2 halves, then
+// lanes c and c^1 swap the off-diagonal elements of each 2x2 block.  Every
+// lane of the quad must execute it.
+__device__ __forceinline__ void quad_transpose(float (&a)[4], int c) {
+  const bool h = (c & 2) != 0;
+  float s0 = h ? a[0] : a[2], s1 = h ? a[1] : a[3];
+  float r0 = quad_perm<0x4E>(s0), r1 = quad_perm<0x4E>(s1);    // lanes [2, 3, 0, 1]
+  if (h) { a[0] = r0; a[1] = r1; } else { a[2] = r0; a[3] = r1; }
+  const bool odd = (c & 1) != 0;
+  s0 = odd ? a[0] : a[1];
+  s1 = odd ? a[2] : a[3];
+  r0 = quad_perm<0xB1>(s0);                                     // lanes [1, 0, 3, 2]
+  r1 = quad_perm<0xB1>(s1);
+  if (odd) { a[0] = r0; a[2] = r1; } else { a[1] = r0; a[3] = r1; }
+}
+
 // One batch of a group tile: copies for later batches, then the MFMAs of
 // this one (see k_gprod).  ring: the workgroup's LDS ring; slot arguments are
 // byte offsets into it.
@@ -606,6 +630,41 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
       // the beta term may come from another pattern's strips (cmap: C strip
       // -> Cin strip), masked to C's blocks; a column quad's map entries are
       // read together before its stores
+      if constexpr (!F64) {
+        // FP32: the lane's column (rows 0..3 of block tb) becomes row cc by a
+        // quad transpose, written 16 bytes per lane (a strip per 16 lanes)
+        const int i = lane >> 4;
+#pragma unroll
+        for (int j = 0; j < GJ; ++j) {
+          const int cs = cstr[wave][GJ * i + j];
+          const bool in = cs >= 0 && ((cmsk[wave][GJ * i + j] >> tb) & 1);
+          float o[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) o[v] = in ? (float)alpha * (float)acc[j][v] : 0.f;
+          quad_transpose(o, cc);
+          if (cs >= 0) {
+            float4* dst = reinterpret_cast<float4*>(reinterpret_cast<float*>(C) + (i64)cs * 64 + tb * 16 + cc * 4);
+            if (cmap) {
+              if (in) {
+#pragma clang fp contract(off)
+                const float4 y = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(Cin) +
+                                                                   cmap[cs] * 64 + tb * 16 + cc * 4);
+                o[0] += (float)beta * y.x;
+                o[1] += (float)beta * y.y;
+                o[2] += (float)beta * y.z;
+                o[3] += (float)beta * y.w;
+              }
+            } else if (beta != (T)0) {
+              const float4 c = *dst;
+              o[0] += (float)beta * c.x;
+              o[1] += (float)beta * c.y;
+              o[2] += (float)beta * c.z;
+              o[3] += (float)beta * c.w;
+            }
+            *dst = make_float4(o[0], o[1], o[2], o[3]);
+          }
+        }
+      } else {
 #pragma unroll
       for (int j = 0; j < GJ; ++j) {
         int mv[4] = {-1, -1, -1, -1};
@@ -637,6 +696,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
           C[idx] = o;
         }
       }
+      }
     }
     // the next tile's prologue rewrites record slots and the slot table
     __builtin_amdgcn_s_waitcnt(0);
@@ -659,29 +719,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
 // ---------------------------------------------------------------------------
 typedef int i2v __attribute__((ext_vector_type(2)));
 
-// Exchange across the 4 lanes of a quad (DPP quad_perm): lane c gets v of
-// lane perm[c].
-template <int CTRL>
-__device__ __forceinline__ float quad_perm(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
-}
-// 4x4 transpose held by the 4 lanes of a quad: on entry lane c (c = lane & 3)
-// holds column c (a[r] = M[r][c]), on exit row c (a[x] = M[c][x]).  Two
-// butterfly rounds: lanes c and c^2 swap the off-diagonal 2x2 halves, then
-// lanes c and c^1 swap the off-diagonal elements of each 2x2 block.  Every
-// lane of the quad must execute it.
-__device__ __forceinline__ void quad_transpose(float (&a)[4], int c) {
-  const bool h = (c & 2) != 0;
-  float s0 = h ? a[0] : a[2], s1 = h ? a[1] : a[3];
-  float r0 = quad_perm<0x4E>(s0), r1 = quad_perm<0x4E>(s1);    // lanes [2, 3, 0, 1]
-  if (h) { a[0] = r0; a[1] = r1; } else { a[2] = r0; a[3] = r1; }
-  const bool odd = (c & 1) != 0;
-  s0 = odd ? a[0] : a[1];
-  s1 = odd ? a[2] : a[3];
-  r0 = quad_perm<0xB1>(s0);                                     // lanes [1, 0, 3, 2]
-  r1 = quad_perm<0xB1>(s1);
-  if (odd) { a[0] = r0; a[2] = r1; } else { a[1] = r0; a[3] = r1; }
-}
 
 template <bool TA>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_gprod_bf16(const GTile* __restrict__ tiles, i64 ntiles,
@@ -889,22 +926,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 #pragma unroll
       for (int j = 0; j < GJ; ++j) {
         const int cs = cstr[wave][GJ * i + j];
-        const bool in = cs >= 0 && ((cmsk[wave][GJ * i + j] >> tb) & 1);
+        const int mk = cmsk[wave][GJ * i + j];
+        const bool in = cs >= 0 && ((mk >> tb) & 1);
         float o[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          o[v] = in ? alpha * acc[j][v] : 0.f;
-          if (cs >= 0) {
-            const i64 idx = (i64)cs * 64 + tb * 16 + v * 4 + cc;
-            if (cmap) {   // the beta term from another pattern's strips (see k_gprod)
-#pragma clang fp contract(off)
-              if (in) o[v] += beta * Cin[(i64)cmp[wave][GJ * i + j] * 64 + (idx & 63)];
-            } else if (beta != 0.f) {
-              o[v] += beta * C[idx];
-            }
-            if (C && ((cmsk[wave][GJ * i + j] >> 4) & 1)) C[idx] = o[v];
-          }
-        }
+        for (int v = 0; v < 4; ++v) o[v] = in ? alpha * acc[j][v] : 0.f;
         // a symmetric result (cmir non-null, half plan) also gets its dropped
         // half: the block-transposed copy of the mirror block (q, p, -n) is the
         // row-major copy of this block (slot tables above)
@@ -916,15 +942,42 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
           const int mbi = tb == 0 ? mbv.x : tb == 1 ? mbv.y : tb == 2 ? mbv.z : mbv.w;
           mirror = mbi >= 0 ? (i64)mbi * 16 : -1;
         }
-        // rounded from the FP32 result as a separate conversion pass would
-        if (outC && cs >= 0 && self)
+        // copies rounded from the FP32 result as a separate conversion pass
+        // would; without a beta term the block-transposed copy is the lane's
+        // column as it stands
+        const bool plain = beta == 0.f && !cmap;
+        if (outC && plain && cs >= 0 && self)
           *reinterpret_cast<ushort4*>(outC + (i64)cs * 64 + tb * 16 + cc * 4) =
               make_ushort4(bf16_rne(o[0]), bf16_rne(o[1]), bf16_rne(o[2]), bf16_rne(o[3]));
-        if (outR || cmir) {
-          quad_transpose(o, cc);             // o[x] = row cc, column x
+        quad_transpose(o, cc);               // o[x] = row cc, column x
+        if (cs >= 0) {
+          const i64 rb = (i64)cs * 64 + tb * 16 + cc * 4;
+          if (cmap) {   // the beta term from another pattern's strips (see k_gprod)
+            if (in) {
+#pragma clang fp contract(off)
+              const float4 y = *reinterpret_cast<const float4*>(Cin + (i64)cmp[wave][GJ * i + j] * 64 + tb * 16 + cc * 4);
+              o[0] += beta * y.x;
+              o[1] += beta * y.y;
+              o[2] += beta * y.z;
+              o[3] += beta * y.w;
+            }
+          } else if (beta != 0.f) {
+            const float4 c = *reinterpret_cast<const float4*>(C + rb);
+            o[0] += beta * c.x;
+            o[1] += beta * c.y;
+            o[2] += beta * c.z;
+            o[3] += beta * c.w;
+          }
+          if (C && ((mk >> 4) & 1)) *reinterpret_cast<float4*>(C + rb) = make_float4(o[0], o[1], o[2], o[3]);
           const ushort4 row = make_ushort4(bf16_rne(o[0]), bf16_rne(o[1]), bf16_rne(o[2]), bf16_rne(o[3]));
-          if (outR && cs >= 0) *reinterpret_cast<ushort4*>(outR + (i64)cs * 64 + tb * 16 + cc * 4) = row;
+          if (outR) *reinterpret_cast<ushort4*>(outR + rb) = row;
           if (mirror >= 0) *reinterpret_cast<ushort4*>(outC + mirror + cc * 4) = row;
+        }
+        if (outC && !plain) {               // back to the column for the block-transposed copy
+          quad_transpose(o, cc);
+          if (cs >= 0 && self)
+            *reinterpret_cast<ushort4*>(outC + (i64)cs * 64 + tb * 16 + cc * 4) =
+                make_ushort4(bf16_rne(o[0]), bf16_rne(o[1]), bf16_rne(o[2]), bf16_rne(o[3]));
         }
       }
     }
