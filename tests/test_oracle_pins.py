@@ -17,7 +17,7 @@ import scipy.sparse as sp
 import oracle
 import workloads
 from tests import _dense
-from tests._sides import onsite_values
+from tests._sides import onsite_values, sym_random
 
 
 # ---------------------------------------------------------------------------
@@ -560,6 +560,34 @@ def test_minimiser_closed_form_projector():
     assert gs[-1] <= 1e-11
     assert abs(Es[-1] - Emin) <= 1e-12 * abs(Emin)
     np.testing.assert_allclose(Lf.val, P, atol=1e-9)
+
+
+def test_minimiser_gradients_mutually_orthogonal():
+    """Near L = 0 the energy is the convex quadratic 6 Tr(L S L H) (S and H
+    positive definite; the cubic term is smaller by a factor |L|).  On a
+    convex quadratic, conjugate gradients with exact line searches make each
+    new gradient orthogonal to all earlier ones, not only to the last one;
+    steepest descent (a Polak-Ribiere beta dropped, of the wrong sign, or with
+    the old gradient in place of the new one, all of which fall back to it)
+    leaves G_2 . G_0 of the order of |G_2| |G_0| (0.6 here).  On a quadratic
+    the Polak-Ribiere and Fletcher-Reeves betas agree, so this does not tell
+    them apart.  Gradients come from lnv_gradient, pinned on its own."""
+    s = _cluster(n=12, edge=9.0, mixed=False, seed=21)
+    r = 5.0
+    inp = _inputs(s, r, r, r)
+    S = inp["S"]
+    H = oracle.Matrix(S.pattern, S.val.copy())                  # H = S: positive definite
+    assert np.linalg.eigvalsh(_dense.to_dense(S)).min() > 0.5
+    L0 = sym_random(inp["L"].pattern, np.random.default_rng(5))
+    L0 = oracle.Matrix(L0.pattern, 1e-4 * L0.val)
+    G = [oracle.lnv_gradient(L0, S, H, r, r, r).val]
+    for k in (1, 2, 3):
+        Lk, _, _ = oracle.lnv_minimise(L0, S, H, r, r, r, max_iter=k)
+        G.append(oracle.lnv_gradient(Lk, S, H, r, r, r).val)
+    for i in range(4):
+        for j in range(i):
+            c = np.dot(G[i], G[j]) / np.sqrt(np.dot(G[i], G[i]) * np.dot(G[j], G[j]))
+            assert abs(c) <= 5e-3, (i, j, c)
 
 
 # ---------------------------------------------------------------------------
