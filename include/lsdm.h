@@ -271,8 +271,9 @@ int lsdm_lnv_profile(lsdm_lnv* lnv, int enable);
  * launches and the useful flops of one launch; clears the record.  F1-F3 make
  * X = LS, M = XL and P = XM; B1 Mbar = X^T Pbar, B2 Xbar = Pbar M, then
  * B3 Xbar += Mbar L, B4 dE/dL = X^T Mbar, B5 dE/dL += Xbar S, or in symmetric
- * mode B1 Y = HX, B3 dE/dL = -4 X^T Y, B5 V += Xbar S with V = 6 Y on L's
- * range (a projection: B4 has no launches and no flops) and dE/dL += V + V^T. */
+ * mode B1 Y = HX, B3 dE/dL = -4 X^T Y, B5 V = Xbar S + 6 Y on L's range (B4
+ * has no launches and no flops) and dE/dL += V + V^T; a symmetric FP64
+ * energy-and-gradient call launches no F3 (its energy skips P). */
 int lsdm_lnv_profile_read(lsdm_lnv* lnv, double* ms, int64_t* launches, double* flops);
 void lsdm_lnv_destroy(lsdm_lnv* lnv);
 
