@@ -5,7 +5,7 @@ import sys
 from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = ["csrc/kernels.hip", "csrc/symbolic.cpp", "csrc/api.cpp"]
+SRC = ["csrc/kernels.hip", "csrc/pattern.hip", "csrc/symbolic.cpp", "csrc/api.cpp"]
 OUT = os.path.join(HERE, "liblsdm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # packed FP32 instructions are disabled for all device code; MFMA accumulators

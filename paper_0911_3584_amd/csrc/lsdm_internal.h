@@ -55,7 +55,24 @@ struct DevBuf {
 
 // image (n0, n1, n2), each in [-128, 127], packed as offset binary so that the
 // packed integer orders lexicographically like the triple
-inline i32 img_pack(int n0, int n1, int n2) { return ((n0 + 128) << 16) | ((n1 + 128) << 8) | (n2 + 128); }
+__host__ __device__ inline i32 img_pack(int n0, int n1, int n2) {
+  return ((n0 + 128) << 16) | ((n1 + 128) << 8) | (n2 + 128);
+}
+
+// Squared distance of a pair for the range test: d = x_j - x_i (+ the lattice
+// translation m T when periodic), with explicit fused multiply-adds so that
+// the host search and the GPU search decide every pair (r^2 <= R^2, inclusive)
+// the same way.
+__host__ __device__ inline double pair_dist2(const double* xi, const double* xj, int m0, int m1, int m2,
+                                             const double* T) {
+  double dx = xj[0] - xi[0], dy = xj[1] - xi[1], dz = xj[2] - xi[2];
+  if (T) {
+    dx += fma((double)m2, T[6], fma((double)m1, T[3], (double)m0 * T[0]));
+    dy += fma((double)m2, T[7], fma((double)m1, T[4], (double)m0 * T[1]));
+    dz += fma((double)m2, T[8], fma((double)m1, T[5], (double)m0 * T[2]));
+  }
+  return fma(dz, dz, fma(dy, dy, dx * dx));
+}
 __host__ __device__ inline int img_c0(i32 p) { return ((p >> 16) & 255) - 128; }
 __host__ __device__ inline int img_c1(i32 p) { return ((p >> 8) & 255) - 128; }
 __host__ __device__ inline int img_c2(i32 p) { return (p & 255) - 128; }

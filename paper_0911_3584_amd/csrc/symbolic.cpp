@@ -23,6 +23,7 @@
 #include "kernels.h"
 #include "lsdm_internal.h"
 #include "plan_common.h"
+#include "search_common.h"
 
 namespace lsdm {
 
@@ -170,6 +171,8 @@ void build_system(lsdm_system* s) {
 // The distance is evaluated from the caller's positions as
 //   (x_j - x_i) + (n0 T0 + n1 T1 + n2 T2), component by component.
 // ---------------------------------------------------------------------------
+bool have_device();
+
 void build_pattern_blocks(lsdm_pattern* p) {
   const lsdm_system* s = p->sys;
   const i32 n = s->n_atoms;
@@ -218,41 +221,33 @@ void build_pattern_blocks(lsdm_pattern* p) {
     std::vector<i64> w(cstart.begin(), cstart.end() - 1);
     for (i32 a = 0; a < n; ++a) catom[w[cid(bin[3 * a], bin[3 * a + 1], bin[3 * a + 2])]++] = a;
   }
+  SearchGeom geom;
+  for (int k = 0; k < 3; ++k) {
+    geom.nb[k] = nb[k];
+    geom.D[k] = D[k];
+  }
+  geom.periodic = s->periodic ? 1 : 0;
+  for (int k = 0; k < 9; ++k) geom.lat[k] = s->lat[k];
+  geom.R2 = R2;
+  if (have_device()) {
+    // the GPU search: counts, the block-index limit, then the sorted rows
+    std::vector<unsigned long long> keys;
+    pattern_search_gpu(geom, s->xyz.data(), wrap.data(), bin.data(), cstart.data(), catom.data(), n, ncell,
+                       p->row_ptr, keys);
+    const i64 nbk = p->row_ptr[n];
+    p->col.resize(nbk);
+    p->img.resize(nbk);
+    parallel_for(n, [&](i64 a) {
+      for (i64 w = p->row_ptr[a]; w < p->row_ptr[a + 1]; ++w) {
+        p->col[w] = (i32)(keys[w] >> 24);
+        p->img[w] = (i32)(keys[w] & 0xffffff);
+      }
+    });
+    return;
+  }
   // every partner (j, image) of row i within R, passed to visit(j, m0, m1, m2)
   auto search_row = [&](i64 i, auto&& visit) {
-    const double xi = s->xyz[3 * i], yi = s->xyz[3 * i + 1], zi = s->xyz[3 * i + 2];
-    for (int d0 = -D[0]; d0 <= D[0]; ++d0)
-      for (int d1 = -D[1]; d1 <= D[1]; ++d1)
-        for (int d2 = -D[2]; d2 <= D[2]; ++d2) {
-          int t[3] = {bin[3 * i] + d0, bin[3 * i + 1] + d1, bin[3 * i + 2] + d2}, sh[3] = {0, 0, 0};
-          bool skip = false;
-          for (int k = 0; k < 3; ++k) {
-            if (s->periodic) {
-              int q = (t[k] >= 0) ? t[k] / nb[k] : -((-t[k] + nb[k] - 1) / nb[k]);
-              sh[k] = q;
-              t[k] -= q * nb[k];
-            } else if (t[k] < 0 || t[k] >= nb[k]) {
-              skip = true;
-            }
-          }
-          if (skip) continue;
-          const i64 c = cid(t[0], t[1], t[2]);
-          for (i64 u = cstart[c]; u < cstart[c + 1]; ++u) {
-            const i32 j = catom[u];
-            int m0 = 0, m1 = 0, m2 = 0;
-            double dx = s->xyz[3 * j] - xi, dy = s->xyz[3 * j + 1] - yi, dz = s->xyz[3 * j + 2] - zi;
-            if (s->periodic) {
-              m0 = sh[0] - wrap[3 * j] + wrap[3 * i];
-              m1 = sh[1] - wrap[3 * j + 1] + wrap[3 * i + 1];
-              m2 = sh[2] - wrap[3 * j + 2] + wrap[3 * i + 2];
-              const double* T = s->lat;
-              dx = dx + ((double)m0 * T[0] + (double)m1 * T[3] + (double)m2 * T[6]);
-              dy = dy + ((double)m0 * T[1] + (double)m1 * T[4] + (double)m2 * T[7]);
-              dz = dz + ((double)m0 * T[2] + (double)m1 * T[5] + (double)m2 * T[8]);
-            }
-            if (dx * dx + dy * dy + dz * dz <= R2) visit(j, m0, m1, m2);
-          }
-        }
+    search_partners(geom, i, s->xyz.data(), wrap.data(), bin.data(), cstart.data(), catom.data(), visit);
   };
   // Size check before any row is stored: when the pair count could reach the
   // block-index limit (2^31 blocks; their values alone would then fill an
@@ -520,7 +515,6 @@ void ensure_maps(lsdm_pattern* p) {
 // groups of TJ).  Device: the steps of every tile (k_plan_steps), so the task
 // list, which is the bulk of a plan, never passes through host memory.
 // ---------------------------------------------------------------------------
-bool have_device();
 
 // Inner list of output rows row0 .. row0+NR-1: the union over the rows of A's
 // blocks (k, m), one entry per (k, m) with the A block of every row (-1 where
