@@ -334,9 +334,9 @@ static lsdm_plan* chain_plan(const lsdm_lnv* L, int w) {
 
 template <class T>
 static void chain_product(lsdm_lnv* L, int w, const T* A, const T* B, T* C, double alpha, double beta, hipStream_t st,
-                          const T* Cin = nullptr, const i64* cmap = nullptr) {
+                          const T* Cin = nullptr, const i64* cmap = nullptr, bool mirrors = false) {
   if (!L->prof) {
-    product<T>(chain_plan(L, w), A, B, C, alpha, beta, st, Cin, cmap);
+    product<T>(chain_plan(L, w), A, B, C, alpha, beta, st, Cin, cmap, mirrors);
     return;
   }
   while (L->ev_pool.size() < L->ev_used + 2) {
@@ -345,7 +345,7 @@ static void chain_product(lsdm_lnv* L, int w, const T* A, const T* B, T* C, doub
     L->ev_pool.push_back(e);
   }
   HIP_CHECK(hipEventRecord(L->ev_pool[L->ev_used], st));
-  product<T>(chain_plan(L, w), A, B, C, alpha, beta, st, Cin, cmap);
+  product<T>(chain_plan(L, w), A, B, C, alpha, beta, st, Cin, cmap, mirrors);
   HIP_CHECK(hipEventRecord(L->ev_pool[L->ev_used + 1], st));
   L->ev_used += 2;
   L->ev_prod.push_back(w);
@@ -377,8 +377,16 @@ static void lnv_forward(lsdm_lnv* L, const double* dL, const double* dS, const d
   user_to_strip<T>(L->pH, dH, wH, 1.0, st);
   user_to_strip<double>(L->pH, dH, wH64, 1.0, st);
   chain_product<T>(L, 0, wL, wS, wX, 1.0, 0.0, st);     // X = LS
-  chain_product<T>(L, 1, wX, wL, wM, 1.0, 0.0, st);     // M = XL
-  if (L->sym) sym_fill<T>(L->pM, wM, st);
+  if (L->sym) {
+    // M = XL on the kept half, the dropped half written as its mirrors
+    if (L->wM_zero != (int)sizeof(T)) {
+      fill<T>(wM, L->pM->n_strips * 64, (T)0, st);
+      L->wM_zero = (int)sizeof(T);
+    }
+    chain_product<T>(L, 1, wX, wL, wM, 1.0, 0.0, st, nullptr, nullptr, true);
+  } else {
+    chain_product<T>(L, 1, wX, wL, wM, 1.0, 0.0, st);   // M = XL
+  }
   if (defer_p) {
     kassembly<T>(L, wM, nullptr, wK, st);                                 // 3 M|_H
     dot_parts(wK, wH64, L->pH->n_strips * 64, L->wE.as<double>(), st);    // <3 M|_H, H>
@@ -496,6 +504,7 @@ static void lnv_forward_bf16(lsdm_lnv* L, const double* dL, const double* dS, co
   // whose epilogue writes the dropped half of a symmetric M as well (the copy
   // of a mirror block is the row-major copy of its kept block)
   chain_product_bf16(L, 1, h(XR), h(LC), wM, 1.0, 0.0, st, nullptr, h(MC), L->d_mneed.as<uint8_t>());
+  L->wM_zero = 0;
   chain_product_bf16(L, 2, h(XR), h(MC), wP, 1.0, 0.0, st);    // P = XM on H's range
   kassembly<float>(L, wM, wP, wK, st);
   dot(wK, wH64, L->pH->n_strips * 64, 2.0, L->wE.as<double>(), dE, st);
@@ -582,6 +591,7 @@ static void lnv_forward_rc(lsdm_lnv* L, const double* dL, const double* dS, cons
   offsite_f32(L->pX, wX, r(RX), st);
   rc_step(L, 1, wX, r(RX), wL, r(RL), wM, 1.0, 0.0, st);       // M = XL
   if (L->sym) sym_fill<double>(L->pM, wM, st);
+  L->wM_zero = 0;
   offsite_f32(L->pM, wM, r(RM), st);
   rc_step(L, 2, wX, r(RX), wM, r(RM), wP, 1.0, 0.0, st);       // P = XM on H's range
   kassembly<double>(L, wM, wP, wK, st);
@@ -668,6 +678,7 @@ static void purify_chain(lsdm_lnv* L, const double* dL, const double* dS, double
   } else {
     product<T>(L->F2, wX, wL, wM2, 1.0, 0.0, st);                    // the chain's M suffices
     if (L->sym) sym_fill<T>(M2, wM2, st);
+    L->wM_zero = 0;
   }
   product<T>(L->P3, wX, wM2, wP2, 1.0, 0.0, st);                     // LSLSL on L's range
   if (L->sym) sym_fill<T>(L->pL, wP2, st);

@@ -13,6 +13,7 @@ double* dot_scratch();
 
 // layout maps of a pattern (built on first use; symbolic.cpp)
 void ensure_maps(lsdm_pattern* p);
+void ensure_mirw(lsdm_pattern* p);
 
 template <class T> void fill(T* p, i64 n, T v, hipStream_t st);
 template <class T> void user_to_strip(const lsdm_pattern* p, const double* user, T* strip, double scale, hipStream_t st);
@@ -23,12 +24,14 @@ template <class T> void sym_fill(const lsdm_pattern* p, T* data, hipStream_t st)
 // out += v + v^T (strip layout, every block of p)
 // dE/dL of symmetric mode into the caller's layout: Lbar (kept half) + V + V^T
 template <class T> void sym_grad_to_user(const lsdm_pattern* p, const T* Lb, const T* V, double* user, hipStream_t st);
-// C = alpha P_C(op(A) B) + beta C in strip layout (B already transposed if the plan says so)
-// C = alpha P_C(op(A) B) + beta C; with cmap (C strip -> Cin strip, nullable) the beta term is
-// beta Cin on the mapped strips, masked to C's blocks, instead of beta C
+// C = alpha P_C(op(A) B) + beta C in strip layout (B already transposed if the plan says so);
+// with cmap (C strip -> Cin strip, nullable) the beta term is beta Cin on the mapped strips,
+// masked to C's blocks, instead of beta C.  mirrors (half-output plan, beta = 0): the epilogue
+// also writes the dropped half, every present block's transpose into its mirror (what
+// sym_fill would copy); absent blocks of dropped strips are not written
 template <class T>
 void product(const lsdm_plan* pl, const T* A, const T* B, T* C, double alpha, double beta, hipStream_t st,
-             const T* Cin = nullptr, const i64* cmap = nullptr);
+             const T* Cin = nullptr, const i64* cmap = nullptr, bool mirrors = false);
 // symbolic pass on the GPU: steps of a plan (count pass fill = 0, fill pass fill = 1)
 void plan_gsteps(const GTile* tiles, i64 ntiles, const GKEnt* kent, const i64* kbeg, const PlanView& v, int fill,
                  i32* counts, GStep* steps, unsigned long long* work);

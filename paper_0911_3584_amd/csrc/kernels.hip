@@ -151,6 +151,29 @@ __global__ void k_sym_fill(T* data, const i64* __restrict__ fill, const i64* __r
   }
 }
 
+// Mirror-write words of a symmetric pattern (lsdm_pattern::d_mirw), one
+// thread per block slot of every strip; dropped strips get 0.
+__global__ void k_mirw(const i32* __restrict__ srow, const i32* __restrict__ squad, const i32* __restrict__ simg,
+                       const uint8_t* __restrict__ smask, const i64* __restrict__ mirror, i32* __restrict__ mw,
+                       i64 nstrips) {
+  for (i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x; g < nstrips * 4; g += (i64)gridDim.x * blockDim.x) {
+    const i64 st = g >> 2;
+    const int t = (int)(g & 3);
+    const i32 q = srow[st], cq = squad[st], n = simg[st];
+    i32 w = 0;
+    if (keep_strip(q, cq, n)) {
+      const bool own = cq == (q >> 2) && n == IMG0;
+      const bool present = (smask[st] >> t) & 1;
+      const i32 qcol = 4 * cq + t;
+      const bool self = !(own && qcol < q && present);
+      const i64 m = mirror[g];
+      const bool wm = present && !(own && qcol <= q) && m >= 0;
+      w = (i32)(((wm ? (m >> 4) + 1 : 0) << 1) | (self ? 1 : 0));
+    }
+    mw[g] = w;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Dense 16x16x4 MFMA forms used by the product kernels: one instruction per
 // active column quad covers the 4 rows of a row quad at once.
@@ -545,7 +568,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
                                                const T* __restrict__ B, T* __restrict__ C,
                                                const uint8_t* __restrict__ cmask, T alpha, T beta, int na_blk,
                                                int nb_str, unsigned long long* __restrict__ queue,
-                                               const T* __restrict__ Cin, const i64* __restrict__ cmap) {
+                                               const T* __restrict__ Cin, const i64* __restrict__ cmap,
+                                               const i32* __restrict__ mirw) {
   typedef typename Mma16<T>::acc_t acc_t;
   typedef GLayout<T> L;
   constexpr bool F64 = sizeof(T) == 8;
@@ -630,6 +654,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
       // the beta term may come from another pattern's strips (cmap: C strip
       // -> Cin strip), masked to C's blocks; a column quad's map entries are
       // read together before its stores
+      // a half-output product of a symmetric result (mirw non-null, no beta
+      // term) also writes the dropped half: word w of the block (d_mirw of the
+      // pattern) gives its mirror block ((w >> 1) - 1) and whether the block
+      // itself is written (w & 1); the mirror's row cc is this block's column cc
       if constexpr (!F64) {
         // FP32: the lane's column (rows 0..3 of block tb) becomes row cc by a
         // quad transpose, written 16 bytes per lane (a strip per 16 lanes)
@@ -637,12 +665,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
 #pragma unroll
         for (int j = 0; j < GJ; ++j) {
           const int cs = cstr[wave][GJ * i + j];
+          const int mw = (mirw && cs >= 0) ? mirw[4 * (i64)cs + tb] : 1;
           const bool in = cs >= 0 && ((cmsk[wave][GJ * i + j] >> tb) & 1);
           float o[4];
 #pragma unroll
           for (int v = 0; v < 4; ++v) o[v] = in ? (float)alpha * (float)acc[j][v] : 0.f;
+          if (mw >> 1)
+            *reinterpret_cast<float4*>(reinterpret_cast<float*>(C) + (i64)((mw >> 1) - 1) * 16 + cc * 4) =
+                make_float4(o[0], o[1], o[2], o[3]);
           quad_transpose(o, cc);
-          if (cs >= 0) {
+          if (cs >= 0 && (mw & 1)) {
             float4* dst = reinterpret_cast<float4*>(reinterpret_cast<float*>(C) + (i64)cs * 64 + tb * 16 + cc * 4);
             if (cmap) {
               if (in) {
@@ -685,6 +717,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
           const i64 idx = (i64)ci.x * 64 + tb * 16 + rr * 4 + cc;
           const bool in = (ci.y >> tb) & 1;
           T o = in ? alpha * acc[j][v] : (T)0;
+          if (mirw) {
+            const int w = mirw[4 * (i64)ci.x + tb];
+            if (w >> 1) C[(i64)((w >> 1) - 1) * 16 + cc * 4 + rr] = o;   // element (cc, rr) of the mirror
+            if (!(w & 1)) continue;
+          }
           if (cmap) {
             // rounded as a separate scaled copy of Cin would be (no fused
             // multiply-add), so the result does not depend on the route
@@ -1318,6 +1355,24 @@ template void sym_fill<double>(const lsdm_pattern*, double*, hipStream_t);
 template void sym_fill<float>(const lsdm_pattern*, float*, hipStream_t);
 template void sym_fill<unsigned short>(const lsdm_pattern*, unsigned short*, hipStream_t);
 
+void ensure_mirw(lsdm_pattern* p) {
+  ensure_maps(p);
+  std::lock_guard<std::mutex> lk(p->maps_mutex);
+  if (p->mirw_ready) return;
+  // the word keeps a block index + 1 in 31 bits
+  if (4 * p->n_strips >= ((i64)1 << 30))
+    LSDM_THROW(LSDM_EUNSUPPORTED, "pattern too large for mirror writes in the product epilogue");
+  p->d_mirw.alloc(sizeof(i32) * std::max<i64>(1, 4 * p->n_strips));
+  if (p->n_strips) {
+    hipLaunchKernelGGL(k_mirw, dim3(grid_for(4 * p->n_strips)), dim3(256), 0, 0, p->d_srow.as<i32>(),
+                       p->d_squad.as<i32>(), p->d_simg.as<i32>(), p->d_smask.as<uint8_t>(), p->d_mirror.as<i64>(),
+                       p->d_mirw.as<i32>(), p->n_strips);
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipDeviceSynchronize());
+  }
+  p->mirw_ready = true;
+}
+
 // Grid of the group kernel: as many workgroups as are resident at once (so
 // every workgroup of an XCD walks its tile range in step with the others), a
 // multiple of 8 (one contiguous tile range per XCD).
@@ -1350,7 +1405,14 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
 
 template <class T>
 void product(const lsdm_plan* pl, const T* A, const T* B, T* C, double alpha, double beta, hipStream_t st,
-             const T* Cin, const i64* cmap) {
+             const T* Cin, const i64* cmap, bool mirrors) {
+  const i32* mirw = nullptr;
+  if (mirrors) {
+    if (!pl->half || beta != 0.0 || cmap)
+      LSDM_THROW(LSDM_EINVAL, "internal: mirror writes need a half-output plan without a beta term");
+    ensure_mirw(const_cast<lsdm_pattern*>(pl->C));
+    mirw = pl->C->d_mirw.as<i32>();
+  }
   if (pl->n_gtiles == 0) return;
   const uint8_t* cm = pl->C->d_smask.as<uint8_t>();
   const GTile* Tl = pl->d_gtiles.as<GTile>();
@@ -1362,15 +1424,15 @@ void product(const lsdm_plan* pl, const T* A, const T* B, T* C, double alpha, do
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, q, 8);
   if (pl->transA)
     hipLaunchKernelGGL((k_gprod<T, true>), dim3(gproduct_grid(k_gprod<T, true>, pl->n_gtiles)), b, 0, st, Tl,
-                       pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta, na, nbs, q, Cin, cmap);
+                       pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta, na, nbs, q, Cin, cmap, mirw);
   else
     hipLaunchKernelGGL((k_gprod<T, false>), dim3(gproduct_grid(k_gprod<T, false>, pl->n_gtiles)), b, 0, st, Tl,
-                       pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta, na, nbs, q, Cin, cmap);
+                       pl->n_gtiles, S, A, B, C, cm, (T)alpha, (T)beta, na, nbs, q, Cin, cmap, mirw);
 }
 template void product<double>(const lsdm_plan*, const double*, const double*, double*, double, double, hipStream_t,
-                              const double*, const i64*);
+                              const double*, const i64*, bool);
 template void product<float>(const lsdm_plan*, const float*, const float*, float*, double, double, hipStream_t,
-                             const float*, const i64*);
+                             const float*, const i64*, bool);
 
 
 void plan_gsteps(const GTile* tiles, i64 ntiles, const GKEnt* kent, const i64* kbeg, const PlanView& v, int fill,

@@ -150,6 +150,14 @@ struct lsdm_pattern {
   lsdm::i64 n_fill = 0;
   lsdm::DevBuf d_fill;
   bool maps_ready = false;          // the maps above are built on first use
+  // writes of a symmetric result's half-output product, one i32 per block
+  // slot of every kept strip: bit 0 set when the block is written in place
+  // (clear for a present block below the diagonal in its row's own quad at
+  // image 0, which is written as the mirror of the block above), bits 1..31
+  // the mirror block's index + 1 when the product also writes that mirror
+  // (its transpose) into the dropped half, else 0.  Built on first use.
+  lsdm::DevBuf d_mirw;
+  bool mirw_ready = false;
   std::mutex maps_mutex;
 };
 
@@ -242,6 +250,11 @@ struct lsdm_lnv {
   // strip-layout workspaces (sized for FP64)
   lsdm::DevBuf wL, wS, wH, wH64, wX, wM, wP, wMb, wXb, wLb, wK;
   lsdm::DevBuf wV;                  // symmetric mode: V = 6 H X - 4 H M S on L's pattern
+  // symmetric mode: F2 writes M's dropped half as mirrors of the kept one
+  // and leaves the absent blocks of dropped strips alone, which F3 and B2
+  // read as zero.  wM_zero is the element size (4 or 8) for which wM was
+  // zeroed and since written only that way; 0 after any other writer
+  int wM_zero = 0;
   lsdm::DevBuf wE;                  // partial sums for the energy
   // map from H's strips to M's strips (K assembly and 6H into Mbar)
   lsdm::DevBuf d_h2m;               // i64 per H strip: M strip index (-1: none)
