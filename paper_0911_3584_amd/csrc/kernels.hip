@@ -38,15 +38,41 @@ __global__ void k_fill(T* __restrict__ p, i64 n, T v) {
   for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) p[i] = v;
 }
 
-// one thread per element of every 4x4 sub-block of the map
+__device__ __forceinline__ void load4(const float* p, float (&v)[4]) {
+  const float4 x = *reinterpret_cast<const float4*>(p);
+  v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+}
+__device__ __forceinline__ void load4(const double* p, double (&v)[4]) {
+  const double2 x = reinterpret_cast<const double2*>(p)[0], y = reinterpret_cast<const double2*>(p)[1];
+  v[0] = x.x; v[1] = x.y; v[2] = y.x; v[3] = y.y;
+}
+
+__device__ __forceinline__ void store4(float* p, const float (&v)[4]) {
+  *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void store4(unsigned short* p, const unsigned short (&v)[4]) {
+  *reinterpret_cast<ushort4*>(p) = make_ushort4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void store4(double* p, const double (&v)[4]) {
+  reinterpret_cast<double2*>(p)[0] = make_double2(v[0], v[1]);
+  reinterpret_cast<double2*>(p)[1] = make_double2(v[2], v[3]);
+}
+
+// one thread per row of every 4x4 sub-block of the map; the row is written
+// whole (its padding columns as zero, which they hold anyway)
 template <class T>
 __global__ void k_user_to_strip(const double* __restrict__ user, T* __restrict__ strip, const i64* __restrict__ su,
                                 const i64* __restrict__ ss, const i32* __restrict__ sh, i64 nsub, double scale) {
-  for (i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x; g < nsub * 16; g += (i64)gridDim.x * blockDim.x) {
-    const i64 sb = g >> 4;
-    const int e = (int)(g & 15), r = e >> 2, c = e & 3;
+  for (i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x; g < nsub * 4; g += (i64)gridDim.x * blockDim.x) {
+    const i64 sb = g >> 2;
+    const int r = (int)(g & 3);
     const int shape = sh[sb], rows = shape & 255, cols = (shape >> 8) & 255, stride = shape >> 16;
-    if (r < rows && c < cols) strip[ss[sb] + r * 4 + c] = (T)(scale * user[su[sb] + (i64)r * stride + c]);
+    if (r >= rows) continue;
+    const double* u = user + su[sb] + (i64)r * stride;
+    T v[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v[c] = c < cols ? (T)(scale * u[c]) : (T)0;
+    store4(strip + ss[sb] + r * 4, v);
   }
 }
 
@@ -74,11 +100,11 @@ __global__ void k_transpose_strips(const T* __restrict__ in, T* __restrict__ out
   }
 }
 
-// dE/dL of symmetric mode in the caller's layout, one thread per element of
-// every 4x4 sub-block: Lbar + V + V^T, where Lbar holds only the kept half (a
-// block of the dropped half is the transpose of its mirror, as the mirror
-// fill would make it; zero when the mirror is absent) and V is whole.  The
-// sums are formed in the order that adding V + V^T to the kept half and then
+// dE/dL of symmetric mode in the caller's layout, one thread per row of every
+// 4x4 sub-block: Lbar + V + V^T, where Lbar holds only the kept half (a block
+// of the dropped half is the transpose of its mirror, as the mirror fill
+// would make it; zero when the mirror is absent) and V is whole.  The sums
+// are formed in the order that adding V + V^T to the kept half and then
 // mirroring it forms them, so either route gives the same bits.
 template <class T>
 __global__ void k_sym_grad_to_user(const T* __restrict__ Lb, const T* __restrict__ V, double* __restrict__ user,
@@ -86,48 +112,50 @@ __global__ void k_sym_grad_to_user(const T* __restrict__ Lb, const T* __restrict
                                    const i32* __restrict__ sh, i64 nsub, const i64* __restrict__ mirror,
                                    const i32* __restrict__ srow, const i32* __restrict__ squad,
                                    const i32* __restrict__ simg) {
-  for (i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x; g < nsub * 16; g += (i64)gridDim.x * blockDim.x) {
-    const i64 sb = g >> 4;
-    const int e = (int)(g & 15), r = e >> 2, c = e & 3;
+  for (i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x; g < nsub * 4; g += (i64)gridDim.x * blockDim.x) {
+    const i64 sb = g >> 2;
+    const int r = (int)(g & 3);
     const int shape = sh[sb], rows = shape & 255, cols = (shape >> 8) & 255, stride = shape >> 16;
-    if (!(r < rows && c < cols)) continue;
+    if (r >= rows) continue;
     const i64 so = ss[sb];                  // strip-layout offset of the block's (0, 0)
     const i64 s = so >> 6;
     const int t = (int)((so >> 4) & 3);
     const i32 p = srow[s], q = squad[s], n = simg[s];
     const bool dropped = !keep_strip(p, q, n) || (q == (p >> 2) && n == IMG0 && 4 * q + t < p);
     const i64 m = mirror[4 * s + t];
-    T x;
+    T x[4] = {(T)0, (T)0, (T)0, (T)0};
     if (!dropped) {
-      T w = V[so + r * 4 + c];
-      if (m >= 0) w += V[m + c * 4 + r];
-      x = Lb[so + r * 4 + c] + w;
+      T v[4], l[4];
+      load4(V + so + r * 4, v);
+      load4(Lb + so + r * 4, l);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        T w = v[c];
+        if (m >= 0) w += V[m + c * 4 + r];
+        x[c] = l[c] + w;
+      }
     } else if (m >= 0) {
-      // the mirror block (kept) after its own update, transposed
-      const i64 mo = m + c * 4 + r;
+      // the mirror block (kept) after its own update, transposed: row r here
+      // is column r there
       const i64 ms = m >> 6;
       const int mt = (int)((m >> 4) & 3);
       const i64 mm = mirror[4 * ms + mt];   // the mirror's mirror: this block
-      T w = V[mo];
-      if (mm >= 0) w += V[mm + r * 4 + c];
-      x = Lb[mo] + w;
-    } else {
-      x = (T)0;
+      T vb[4] = {(T)0, (T)0, (T)0, (T)0};
+      if (mm >= 0) load4(V + mm + r * 4, vb);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        T w = V[m + c * 4 + r];
+        if (mm >= 0) w += vb[c];
+        x[c] = Lb[m + c * 4 + r] + w;
+      }
     }
-    user[su[sb] + (i64)r * stride + c] = (double)x;
+    double* u = user + su[sb] + (i64)r * stride;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (c < cols) u[c] = (double)x[c];
   }
 }
 
-__device__ __forceinline__ void store4(float* p, const float (&v)[4]) {
-  *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
-}
-__device__ __forceinline__ void store4(unsigned short* p, const unsigned short (&v)[4]) {
-  *reinterpret_cast<ushort4*>(p) = make_ushort4(v[0], v[1], v[2], v[3]);
-}
-__device__ __forceinline__ void store4(double* p, const double (&v)[4]) {
-  reinterpret_cast<double2*>(p)[0] = make_double2(v[0], v[1]);
-  reinterpret_cast<double2*>(p)[1] = make_double2(v[2], v[3]);
-}
 
 // The dropped half of a symmetric result from its kept half, in place: one
 // thread per row of a block to fill (the list holds strip << 4 | block mask),
@@ -1307,7 +1335,7 @@ template <class T>
 void user_to_strip(const lsdm_pattern* p, const double* user, T* strip, double scale, hipStream_t st) {
   ensure_maps(const_cast<lsdm_pattern*>(p));
   if (p->n_sub == 0) return;
-  hipLaunchKernelGGL(k_user_to_strip<T>, dim3(grid_for(p->n_sub * 16)), dim3(256), 0, st, user, strip,
+  hipLaunchKernelGGL(k_user_to_strip<T>, dim3(grid_for(p->n_sub * 4)), dim3(256), 0, st, user, strip,
                      p->d_sub_user.as<i64>(), p->d_sub_strip.as<i64>(), p->d_sub_shape.as<i32>(), p->n_sub, scale);
 }
 template void user_to_strip<double>(const lsdm_pattern*, const double*, double*, double, hipStream_t);
@@ -1337,7 +1365,7 @@ template <class T>
 void sym_grad_to_user(const lsdm_pattern* p, const T* Lb, const T* V, double* user, hipStream_t st) {
   ensure_maps(const_cast<lsdm_pattern*>(p));
   if (p->n_sub == 0) return;
-  hipLaunchKernelGGL(k_sym_grad_to_user<T>, dim3(grid_for(p->n_sub * 16)), dim3(256), 0, st, Lb, V, user,
+  hipLaunchKernelGGL(k_sym_grad_to_user<T>, dim3(grid_for(p->n_sub * 4)), dim3(256), 0, st, Lb, V, user,
                      p->d_sub_user.as<i64>(), p->d_sub_strip.as<i64>(), p->d_sub_shape.as<i32>(), p->n_sub,
                      p->d_mirror.as<i64>(), p->d_srow.as<i32>(), p->d_squad.as<i32>(), p->d_simg.as<i32>());
 }

@@ -211,6 +211,39 @@ def test_lnv_deterministic():
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
+def test_symmetric_handle_mode_sequence():
+    """One symmetric handle runs every precision mode, the energy-only chain
+    and the McWeeny step (whose LSL shares M's workspace here, rH = rL), in
+    turn, twice over: each call's second result equals its first bit for
+    bit, whatever ran on the shared workspaces in between.  The FP32 and FP64
+    chains write M's dropped half from F2's epilogue and rely on the absent
+    blocks of its dropped strips holding zeros in their own element type."""
+    s, rS, rH, rL = CHAIN_CASES["si64_rl12"]()
+    lnv, v = _chain_setup(s, rS, rH, rL, symmetric=True)
+    L, S, H = T(v["L"]), T(v["S"]), T(v["H"])
+    calls = {
+        "fp32": lambda: lnv.energy_grad(L, S, H, prec="fp32"),
+        "fp64": lambda: lnv.energy_grad(L, S, H, prec="fp64"),
+        "energy64": lambda: lnv.energy(L, S, H, prec="fp64", want_K=True),
+        "purify64": lambda: (lnv.purify(L, S, prec="fp64"),),
+        "bf16": lambda: lnv.energy_grad(L, S, H, prec="bf16"),
+        "energy32": lambda: lnv.energy(L, S, H, prec="fp32", want_K=True),
+        "fp32_rc": lambda: lnv.energy_grad(L, S, H, prec="fp32_rc"),
+        "purify32": lambda: (lnv.purify(L, S, prec="fp32"),),
+    }
+    first = {}
+    for rep in range(2):
+        for name, call in calls.items():
+            r = [x.cpu().numpy().copy() for x in call()]
+            if rep == 0:
+                first[name] = r
+            else:
+                assert all(np.array_equal(a, b) for a, b in zip(first[name], r)), name
+    ref = oracle.lnv_energy(*(oracle.make_inputs(s, rS, rH, rL)[w] for w in "LSH"), rS, rH, rL)["E"]
+    assert abs(first["fp64"][0].item() - ref) <= TOL64 * abs(ref)
+    assert abs(first["energy64"][0].item() - ref) <= TOL64 * abs(ref)
+
+
 def test_autograd_function():
     s, rS, rH, rL = CHAIN_CASES["si64_jitter_rl16"]()
     lnv, v = _chain_setup(s, rS, rH, rL)
