@@ -76,14 +76,21 @@ __global__ void k_user_to_strip(const double* __restrict__ user, T* __restrict__
   }
 }
 
+// one thread per row of every 4x4 sub-block of the map
 template <class T>
 __global__ void k_strip_to_user(const T* __restrict__ strip, double* __restrict__ user, const i64* __restrict__ su,
                                 const i64* __restrict__ ss, const i32* __restrict__ sh, i64 nsub) {
-  for (i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x; g < nsub * 16; g += (i64)gridDim.x * blockDim.x) {
-    const i64 sb = g >> 4;
-    const int e = (int)(g & 15), r = e >> 2, c = e & 3;
+  for (i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x; g < nsub * 4; g += (i64)gridDim.x * blockDim.x) {
+    const i64 sb = g >> 2;
+    const int r = (int)(g & 3);
     const int shape = sh[sb], rows = shape & 255, cols = (shape >> 8) & 255, stride = shape >> 16;
-    if (r < rows && c < cols) user[su[sb] + (i64)r * stride + c] = (double)strip[ss[sb] + r * 4 + c];
+    if (r >= rows) continue;
+    T v[4];
+    load4(strip + ss[sb] + r * 4, v);
+    double* u = user + su[sb] + (i64)r * stride;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (c < cols) u[c] = (double)v[c];
   }
 }
 
@@ -237,19 +244,26 @@ __device__ __forceinline__ unsigned short bf16_rne(float f) {
 }
 
 // caller's block layout (FP64) -> bf16 strips, rounded through FP32 as the
-// FP32 strips would be: R keeps the layout, C transposes every 4x4 block
+// FP32 strips would be: R keeps the layout, C transposes every 4x4 block.
+// One thread per row of every sub-block; the row's padding columns are
+// written as zero, which they hold anyway.
 __global__ void k_user_to_bf16(const double* __restrict__ user, unsigned short* __restrict__ outR,
                                unsigned short* __restrict__ outC, const i64* __restrict__ su,
                                const i64* __restrict__ ss, const i32* __restrict__ sh, i64 nsub) {
-  for (i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x; g < nsub * 16; g += (i64)gridDim.x * blockDim.x) {
-    const i64 sb = g >> 4;
-    const int e = (int)(g & 15), r = e >> 2, c = e & 3;
+  for (i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x; g < nsub * 4; g += (i64)gridDim.x * blockDim.x) {
+    const i64 sb = g >> 2;
+    const int r = (int)(g & 3);
     const int shape = sh[sb], rows = shape & 255, cols = (shape >> 8) & 255, stride = shape >> 16;
-    if (r < rows && c < cols) {
-      const unsigned short v = bf16_rne((float)user[su[sb] + (i64)r * stride + c]);
-      if (outR) outR[ss[sb] + r * 4 + c] = v;
-      if (outC) outC[ss[sb] + c * 4 + r] = v;
-    }
+    if (r >= rows) continue;
+    const double* u = user + su[sb] + (i64)r * stride;
+    unsigned short v[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v[c] = c < cols ? bf16_rne((float)u[c]) : (unsigned short)0;
+    const i64 o = ss[sb];
+    if (outR) store4(outR + o + r * 4, v);
+    if (outC)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) outC[o + c * 4 + r] = v[c];
   }
 }
 
@@ -1345,7 +1359,7 @@ template <class T>
 void strip_to_user(const lsdm_pattern* p, const T* strip, double* user, hipStream_t st) {
   ensure_maps(const_cast<lsdm_pattern*>(p));
   if (p->n_sub == 0) return;
-  hipLaunchKernelGGL(k_strip_to_user<T>, dim3(grid_for(p->n_sub * 16)), dim3(256), 0, st, strip, user,
+  hipLaunchKernelGGL(k_strip_to_user<T>, dim3(grid_for(p->n_sub * 4)), dim3(256), 0, st, strip, user,
                      p->d_sub_user.as<i64>(), p->d_sub_strip.as<i64>(), p->d_sub_shape.as<i32>(), p->n_sub);
 }
 template void strip_to_user<double>(const lsdm_pattern*, const double*, double*, hipStream_t);
@@ -1547,7 +1561,7 @@ void user_to_bf16(const lsdm_pattern* p, const double* user, unsigned short* out
                   hipStream_t st) {
   ensure_maps(const_cast<lsdm_pattern*>(p));
   if (p->n_sub == 0) return;
-  hipLaunchKernelGGL(k_user_to_bf16, dim3(grid_for(p->n_sub * 16)), dim3(256), 0, st, user, outR, outC,
+  hipLaunchKernelGGL(k_user_to_bf16, dim3(grid_for(p->n_sub * 4)), dim3(256), 0, st, user, outR, outC,
                      p->d_sub_user.as<i64>(), p->d_sub_strip.as<i64>(), p->d_sub_shape.as<i32>(), p->n_sub);
 }
 
