@@ -377,7 +377,7 @@ static void lnv_forward(lsdm_lnv* L, const double* dL, const double* dS, const d
   user_to_strip<T>(L->pH, dH, wH, 1.0, st);
   user_to_strip<double>(L->pH, dH, wH64, 1.0, st);
   chain_product<T>(L, 0, wL, wS, wX, 1.0, 0.0, st);     // X = LS
-  if (L->sym) {
+  if (L->sym && mirw_fits(L->pM)) {
     // M = XL on the kept half, the dropped half written as its mirrors
     if (L->wM_zero != (int)sizeof(T)) {
       fill<T>(wM, L->pM->n_strips * 64, (T)0, st);
@@ -386,6 +386,10 @@ static void lnv_forward(lsdm_lnv* L, const double* dL, const double* dS, const d
     chain_product<T>(L, 1, wX, wL, wM, 1.0, 0.0, st, nullptr, nullptr, true);
   } else {
     chain_product<T>(L, 1, wX, wL, wM, 1.0, 0.0, st);   // M = XL
+    if (L->sym) {                                        // beyond the mirror words' reach: a fill pass
+      sym_fill<T>(L->pM, wM, st);
+      L->wM_zero = 0;
+    }
   }
   if (defer_p) {
     kassembly<T>(L, wM, nullptr, wK, st);                                 // 3 M|_H

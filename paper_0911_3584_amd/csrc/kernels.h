@@ -14,6 +14,8 @@ double* dot_scratch();
 // layout maps of a pattern (built on first use; symbolic.cpp)
 void ensure_maps(lsdm_pattern* p);
 void ensure_mirw(lsdm_pattern* p);
+// the mirror words (block index + 1 in 31 bits) reach every block of the pattern
+inline bool mirw_fits(const lsdm_pattern* p) { return 4 * p->n_strips < ((i64)1 << 30); }
 
 template <class T> void fill(T* p, i64 n, T v, hipStream_t st);
 template <class T> void user_to_strip(const lsdm_pattern* p, const double* user, T* strip, double scale, hipStream_t st);

@@ -1401,9 +1401,8 @@ void ensure_mirw(lsdm_pattern* p) {
   ensure_maps(p);
   std::lock_guard<std::mutex> lk(p->maps_mutex);
   if (p->mirw_ready) return;
-  // the word keeps a block index + 1 in 31 bits
-  if (4 * p->n_strips >= ((i64)1 << 30))
-    LSDM_THROW(LSDM_EUNSUPPORTED, "pattern too large for mirror writes in the product epilogue");
+  if (!mirw_fits(p))
+    LSDM_THROW(LSDM_EUNSUPPORTED, "internal: pattern too large for mirror writes in the product epilogue");
   p->d_mirw.alloc(sizeof(i32) * std::max<i64>(1, 4 * p->n_strips));
   if (p->n_strips) {
     hipLaunchKernelGGL(k_mirw, dim3(grid_for(4 * p->n_strips)), dim3(256), 0, 0, p->d_srow.as<i32>(),
