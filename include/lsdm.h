@@ -29,7 +29,8 @@
  *     passed to the library are DEVICE pointers to doubles in this layout.
  *   Ownership: handles are created and destroyed by the library; value
  *     buffers belong to the caller and are never freed by the library.  Device
- *     workspace is allocated by the library (hipMalloc) when a handle is
+ *     workspace is allocated by the library (hipMalloc, or the caller's
+ *     allocator: lsdm_set_allocator) when a handle is
  *     created or first used and released when it is destroyed: a plan keeps
  *     the operand workspaces of its stand-alone multiplies and the two plans
  *     of its adjoint, so repeated calls on one plan allocate nothing.
@@ -49,6 +50,7 @@
 #ifndef LSDM_H
 #define LSDM_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -78,6 +80,27 @@ enum {
   LSDM_FP32_RC = 3  /* FP32 products of the off-site parts plus FP64 on-site
                        (block-diagonal) terms, see lsdm_multiply */
 };
+
+/* ---- device memory ----------------------------------------------------- */
+/* Allocator of the library's internal device workspaces (value buffers stay
+ * the caller's).  With alloc and release both non-NULL, every later workspace
+ * allocation calls alloc(bytes, ctx), which must return memory of the
+ * current HIP device, at least `bytes` long and aligned to 256 bytes, or
+ * NULL: the library call that asked then fails with LSDM_ENOMEM (and with
+ * LSDM_EINVAL for a misaligned pointer, which it gives back at once).  A
+ * workspace goes back through release(ptr, ctx) of the allocator that made
+ * it, when its handle is destroyed or the workspace is resized.  Both NULL
+ * restores hipMalloc / hipFree.  The setting is process-wide.  Buffers made
+ * before a change keep the allocator that made them, so a pair must stay
+ * callable until every handle that used it is destroyed.  Both functions are
+ * called on the thread that calls the library, never from device code or
+ * a stream callback.  A workspace is used on the streams of the calls that
+ * use it, so a stream-ordered allocator must not hand released memory out
+ * again before that work is complete.
+ * Errors: LSDM_EINVAL (exactly one of alloc and release NULL). */
+typedef void* (*lsdm_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*lsdm_free_fn)(void* ptr, void* ctx);
+int lsdm_set_allocator(lsdm_alloc_fn alloc, lsdm_free_fn release, void* ctx);
 
 /* ---- system ------------------------------------------------------------ */
 /* Atoms with orbital blocks (eq. 1: support functions i-alpha on atom i).

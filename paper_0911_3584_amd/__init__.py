@@ -132,6 +132,32 @@ class Plan:
             self._h = None
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_allocators = []   # every pair ever set stays alive: buffers keep the allocator that made them
+
+
+def set_allocator(alloc=None, release=None):
+    """Route the library's device workspaces through alloc(nbytes) -> device
+    pointer (int; None or 0 for failure) and release(ptr) (lsdm_set_allocator);
+    no arguments restores hipMalloc."""
+    if (alloc is None) != (release is None):
+        raise ValueError("set_allocator needs both alloc and release, or neither")
+    if alloc is None:
+        check(lib().lsdm_set_allocator(None, None, None))
+        return
+    a = _ALLOC_FN(lambda n, ctx: alloc(int(n)) or None)
+    f = _FREE_FN(lambda ptr, ctx: release(int(ptr)))
+    _allocators.append((a, f))
+    check(lib().lsdm_set_allocator(ctypes.cast(a, ctypes.c_void_p), ctypes.cast(f, ctypes.c_void_p), None))
+
+
+def use_torch_allocator():
+    """set_allocator with torch's caching allocator (current device and stream)."""
+    import torch
+    set_allocator(lambda n: torch.cuda.caching_allocator_alloc(n), torch.cuda.caching_allocator_delete)
+
+
 def multiply(plan, A, B, C, alpha=1.0, beta=0.0, prec="fp64", stream=None):
     """C = alpha P_C(op(A) op(B)) + beta C (device tensors in block layout)."""
     check(lib().lsdm_multiply(plan._h, _prec(prec), float(alpha), _dev(A, plan.A.n_values, "A"),

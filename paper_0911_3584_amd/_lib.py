@@ -43,6 +43,7 @@ SIGNATURES = {
     "lsdm_lnv_profile": (_I, [_P, _I]),
     "lsdm_lnv_profile_read": (_I, [_P, _P, _P, _P]),
     "lsdm_lnv_destroy": (None, [_P]),
+    "lsdm_set_allocator": (_I, [_P, _P, _P]),
     "lsdm_last_error": (ctypes.c_char_p, []),
     "lsdm_version": (ctypes.c_char_p, []),
 }

@@ -64,18 +64,53 @@ static void require_device() {
   if (!have_device()) LSDM_THROW(LSDM_EDEVICE, "no HIP device: compute calls need an MI355X (gfx950)");
 }
 
+// the caller's workspace allocator (lsdm_set_allocator); null: hipMalloc
+static std::mutex g_alloc_mu;
+static lsdm_alloc_fn g_alloc = nullptr;
+static lsdm_free_fn g_free = nullptr;
+static void* g_alloc_ctx = nullptr;
+
 DevBuf::~DevBuf() {
-  if (p) (void)hipFree(p);
+  if (!p) return;
+  if (rel) rel(p, rel_ctx);
+  else (void)hipFree(p);
+}
+void DevBuf::release() {
+  if (!p) return;
+  void* q = p;
+  p = nullptr;
+  bytes = 0;
+  if (rel) rel(q, rel_ctx);
+  else HIP_CHECK(hipFree(q));
 }
 void DevBuf::alloc(size_t nbytes) {
-  if (p) {
-    HIP_CHECK(hipFree(p));
-    p = nullptr;
-  }
-  bytes = 0;
+  release();
   if (nbytes == 0) nbytes = 16;
   if (!have_device()) return;
-  HIP_CHECK(hipMalloc(&p, nbytes));
+  lsdm_alloc_fn a;
+  lsdm_free_fn f;
+  void* ctx;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    a = g_alloc;
+    f = g_free;
+    ctx = g_alloc_ctx;
+  }
+  if (a) {
+    void* q = a(nbytes, ctx);
+    if (!q) LSDM_THROW(LSDM_ENOMEM, "the caller's allocator returned NULL for " + std::to_string(nbytes) + " bytes");
+    if (reinterpret_cast<uintptr_t>(q) & 255u) {
+      f(q, ctx);
+      LSDM_THROW(LSDM_EINVAL, "the caller's allocator returned memory not aligned to 256 bytes");
+    }
+    p = q;
+    rel = f;
+    rel_ctx = ctx;
+  } else {
+    HIP_CHECK(hipMalloc(&p, nbytes));
+    rel = nullptr;
+    rel_ctx = nullptr;
+  }
   bytes = nbytes;
 }
 void DevBuf::upload(const void* host, size_t nbytes) {
@@ -706,6 +741,17 @@ using namespace lsdm;
 
 extern "C" {
 
+int lsdm_set_allocator(lsdm_alloc_fn alloc, lsdm_free_fn release, void* ctx) {
+  return guarded([&] {
+    if ((alloc == nullptr) != (release == nullptr))
+      LSDM_THROW(LSDM_EINVAL, "lsdm_set_allocator: alloc and release must both be set or both be NULL");
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc = alloc;
+    g_free = release;
+    g_alloc_ctx = alloc ? ctx : nullptr;
+  });
+}
+
 const char* lsdm_last_error(void) { return g_last_error.c_str(); }
 const char* lsdm_version(void) { return "lsdm 0.1 gfx950"; }
 
@@ -1073,7 +1119,7 @@ int lsdm_lnv_minimise(lsdm_lnv* L, int prec, double* dL, const double* dS, const
         lincomb(D.as<double>(), Gn.as<double>(), Gn.as<double>(), -1.0, 0.0, n, st);
         slope = -gn2;
       }
-      std::swap(G.p, Gn.p);
+      G.swap(Gn);
       g2 = gn2;
       gnorm_hist[it] = std::sqrt(g2);
       h = t;

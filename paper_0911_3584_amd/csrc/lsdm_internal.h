@@ -16,6 +16,7 @@
 #include <cstdint>
 #include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/lsdm.h"
@@ -41,15 +42,27 @@ void set_error(int code, const std::string& msg);
   } while (0)
 
 // -------- device buffers ---------------------------------------------------
+// Memory comes from hipMalloc or from the caller's allocator set with
+// lsdm_set_allocator; a buffer keeps the release function of the allocator
+// that made it.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  lsdm_free_fn rel = nullptr;       // null: hipFree
+  void* rel_ctx = nullptr;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf();
   void alloc(size_t nbytes);
+  void release();
   void upload(const void* host, size_t nbytes);
+  void swap(DevBuf& o) {              // exchange buffers with their release functions
+    std::swap(p, o.p);
+    std::swap(bytes, o.bytes);
+    std::swap(rel, o.rel);
+    std::swap(rel_ctx, o.rel_ctx);
+  }
   template <class T> T* as() const { return reinterpret_cast<T*>(p); }
 };
 

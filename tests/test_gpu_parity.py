@@ -244,6 +244,44 @@ def test_symmetric_handle_mode_sequence():
     assert abs(first["energy64"][0].item() - ref) <= TOL64 * abs(ref)
 
 
+def test_caller_allocator_serves_every_workspace():
+    """With torch's caching allocator set through lsdm_set_allocator, a
+    symmetric handle's workspaces (patterns, plans, chain buffers, lazy maps)
+    come from it and all go back to it when the handle is destroyed; the
+    results equal those of a handle on hipMalloc bit for bit."""
+    import gc
+    s, rS, rH, rL = CHAIN_CASES["si64_jitter_rl16"]()
+    ref, v = _chain_setup(s, rS, rH, rL, symmetric=True)
+    L, S, H = T(v["L"]), T(v["S"]), T(v["H"])
+    want = {p: [x.cpu().numpy().copy() for x in ref.energy_grad(L, S, H, prec=p)] for p in ("fp64", "fp32", "bf16")}
+    live, made = {}, [0]
+
+    def alloc(n):
+        ptr = torch.cuda.caching_allocator_alloc(n)
+        live[ptr] = n
+        made[0] += 1
+        return ptr
+
+    def release(ptr):
+        assert ptr in live, ptr
+        del live[ptr]
+        torch.cuda.caching_allocator_delete(ptr)
+
+    lsdm.set_allocator(alloc, release)
+    try:
+        lnv, _ = _chain_setup(s, rS, rH, rL, symmetric=True)
+        for p, w in want.items():
+            got = [x.cpu().numpy() for x in lnv.energy_grad(L, S, H, prec=p)]
+            assert all(np.array_equal(a, b) for a, b in zip(w, got)), p
+        assert made[0] > 0 and live
+        torch.cuda.synchronize()
+        del lnv
+        gc.collect()
+        assert not live, f"{len(live)} workspaces not given back"
+    finally:
+        lsdm.set_allocator()
+
+
 def test_autograd_function():
     s, rS, rH, rL = CHAIN_CASES["si64_jitter_rl16"]()
     lnv, v = _chain_setup(s, rS, rH, rL)

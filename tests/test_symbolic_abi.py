@@ -211,6 +211,32 @@ def test_errors():
         assert full.patterns[w].n_values == sym.patterns[w].n_values
 
 
+def test_allocator_arguments():
+    """lsdm_set_allocator takes both functions or neither; without a device
+    no workspace is allocated, so the caller's allocator is never called."""
+    L = lsdm.lib()
+    a = lsdm._ALLOC_FN(lambda n, ctx: None)
+    f = lsdm._FREE_FN(lambda ptr, ctx: None)
+    assert L.lsdm_set_allocator(ctypes.cast(a, ctypes.c_void_p), None, None) == lsdm._lib.EINVAL
+    assert L.lsdm_set_allocator(None, ctypes.cast(f, ctypes.c_void_p), None) == lsdm._lib.EINVAL
+    assert L.lsdm_set_allocator(None, None, None) == lsdm._lib.OK
+    with pytest.raises(ValueError):
+        lsdm.set_allocator(lambda n: 0, None)
+    import torch
+    if torch.cuda.is_available():
+        return
+    calls = []
+    lsdm.set_allocator(lambda n: calls.append(n), lambda ptr: None)
+    try:
+        gs = lsdm.System.from_workload(workloads.diamond(1))
+        lnv = lsdm.LNV(gs, 4.0, 6.0, 6.0, symmetric=True)
+        assert lnv.info(True)[0] > 0
+        del lnv, gs
+    finally:
+        lsdm.set_allocator()
+    assert calls == []
+
+
 def test_pattern_beyond_the_block_limit_is_enomem():
     """A finite range whose pattern would exceed the library's size limit
     (2^31 blocks, whose values alone would fill the device) is refused with
