@@ -115,17 +115,19 @@ void lsdm_system_destroy(lsdm_system* sys);
 
 /* ---- range patterns (symbolic pass, step 1) ----------------------------- */
 /* Pattern of all blocks (i, j, n) within `range` (the locality cutoff stated
- * after eq. 3), found by a cell-list neighbour search on the host, then laid
- * out in the internal strip layout on the device.
+ * after eq. 3), found by a cell-list neighbour search (on the device when
+ * there is one, one thread per atom, rows key-sorted; on the host otherwise),
+ * then laid out in the internal strip layout on the device.
  * Errors: LSDM_EINVAL (range < 0 or not finite), LSDM_ENOMEM (the pattern
  * would exceed the device or an index limit), LSDM_EDEVICE. */
 int lsdm_pattern_create(const lsdm_system* sys, double range, lsdm_pattern** out);
 /* Number of blocks and of values (doubles) of the block layout. */
 int lsdm_pattern_info(const lsdm_pattern* p, int64_t* n_blocks, int64_t* n_values);
 /* Copy the pattern to HOST arrays: row_ptr[n_atoms+1], col[n_blocks],
- * img3[3*n_blocks], val_off[n_blocks].  Any output pointer may be NULL. */
+ * img3[3*n_blocks] (the image n of each block, components in -127..127),
+ * val_off[n_blocks].  Any output pointer may be NULL. */
 int lsdm_pattern_export(const lsdm_pattern* p, int64_t* row_ptr, int32_t* col,
-                        int32_t* img3, int64_t* val_off);
+                        int8_t* img3, int64_t* val_off);
 void lsdm_pattern_destroy(lsdm_pattern* p);
 
 /* ---- truncated products (symbolic pass step 2 and the product) ---------- */

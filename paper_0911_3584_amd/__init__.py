@@ -96,7 +96,7 @@ class Pattern:
         if self._exp is None:
             rp = np.zeros(self.system.n + 1, np.int64)
             col = np.zeros(self.n_blocks, np.int32)
-            img = np.zeros((self.n_blocks, 3), np.int32)
+            img = np.zeros((self.n_blocks, 3), np.int8)
             off = np.zeros(self.n_blocks, np.int64)
             check(lib().lsdm_pattern_export(self._h, _ptr(rp), _ptr(col), _ptr(img), _ptr(off)))
             self._exp = (rp, col, img, off)

@@ -799,7 +799,7 @@ int lsdm_pattern_info(const lsdm_pattern* p, int64_t* n_blocks, int64_t* n_value
   });
 }
 
-int lsdm_pattern_export(const lsdm_pattern* p, int64_t* row_ptr, int32_t* col, int32_t* img3, int64_t* val_off) {
+int lsdm_pattern_export(const lsdm_pattern* p, int64_t* row_ptr, int32_t* col, int8_t* img3, int64_t* val_off) {
   return guarded([&] {
     if (!p) LSDM_THROW(LSDM_EINVAL, "null pattern");
     if (row_ptr) std::memcpy(row_ptr, p->row_ptr.data(), sizeof(int64_t) * p->row_ptr.size());
@@ -807,9 +807,9 @@ int lsdm_pattern_export(const lsdm_pattern* p, int64_t* row_ptr, int32_t* col, i
     if (val_off) std::memcpy(val_off, p->val_off.data(), sizeof(int64_t) * p->val_off.size());
     if (img3)
       for (size_t b = 0; b < p->img.size(); ++b) {
-        img3[3 * b] = img_c0(p->img[b]);
-        img3[3 * b + 1] = img_c1(p->img[b]);
-        img3[3 * b + 2] = img_c2(p->img[b]);
+        img3[3 * b] = (int8_t)img_c0(p->img[b]);
+        img3[3 * b + 1] = (int8_t)img_c1(p->img[b]);
+        img3[3 * b + 2] = (int8_t)img_c2(p->img[b]);
       }
   });
 }
