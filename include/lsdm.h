@@ -35,13 +35,14 @@
  *     the operand workspaces of its stand-alone multiplies and the two plans
  *     of its adjoint, so repeated calls on one plan allocate nothing.
  *   Streams: compute calls enqueue work on `stream` (a hipStream_t, NULL = the
- *     default stream).  The multiplies and the LNV energy, gradient, shift and
- *     electron calls return without waiting; *_create calls, lsdm_dot, the
- *     line search and the minimiser (which read scalars back or release
- *     buffers) synchronise, and so does the first call that builds a lazy
+ *     default stream).  The multiplies, the dots and the LNV energy,
+ *     gradient, shift and electron calls return without waiting; *_create
+ *     calls, the line search and the minimiser (which read scalars back)
+ *     synchronise, and so does the first call that builds a lazy
  *     part of a handle (layout maps, adjoint plans, residual-mode maps, the
- *     S-in-H map).  Calls on one handle must not run concurrently, on one
- *     stream or several: they share the handle's workspaces.
+ *     S-in-H map, the dot's partial sums).  Calls on one handle must not run
+ *     concurrently, on one stream or several: they share the handle's
+ *     workspaces (calls queued one after another on one stream are fine).
  *   Errors: every call returns LSDM_OK (0) or a negative status; no exception
  *     crosses the ABI; lsdm_last_error() returns a message for the calling
  *     thread's last failure.  A failed call leaves its outputs undefined and
@@ -176,7 +177,9 @@ int lsdm_multiply_adjoint(const lsdm_plan* plan, int prec, const double* dCbar, 
 
 /* *dOut = sum over the blocks of p of <A_b, B_b>_F (= Tr(A B^T) over the
  * pattern; Tr(AB) for symmetric B).  FP64 with per-thread compensated sums and
- * a fixed-order tree, so the result is bitwise reproducible.  dOut: device. */
+ * a fixed-order tree, so the result is bitwise reproducible.  dOut: device.
+ * Returns without waiting; its partial sums live on the pattern (16 KiB,
+ * allocated on the first call), so later calls allocate nothing. */
 int lsdm_dot(const lsdm_pattern* p, const double* dA, const double* dB, double* dOut, void* stream);
 /* lsdm_dot without allocation, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid

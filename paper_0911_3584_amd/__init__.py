@@ -177,9 +177,10 @@ def multiply_adjoint(plan, Cbar, A, B, Abar=None, Bbar=None, prec="fp64", stream
 
 def dot(pattern, A, B, out=None, stream=None, noalloc=False):
     """sum over pattern blocks of <A_b, B_b> as a one-element device tensor.
-    noalloc=True: the variant that allocates nothing and does not synchronise
-    (its partial sums sit in the library's static scratch; concurrent calls
-    on one device race), for graph capture and serving loops."""
+    Asynchronous; its partial sums live on the pattern (allocated on the
+    first call).  noalloc=True: the variant that allocates nothing, not even on
+    its first call (its partial sums sit in the library's static scratch;
+    concurrent calls on one device race), for graph capture and serving loops."""
     import torch
     if out is None:
         out = torch.empty(1, dtype=torch.float64, device=A.device)

@@ -894,12 +894,13 @@ int lsdm_dot(const lsdm_pattern* p, const double* dA, const double* dB, double* 
   return guarded([&] {
     require_device();
     if (!p || !dA || !dB || !dOut) LSDM_THROW(LSDM_EINVAL, "null argument");
-    DevBuf part;
-    part.alloc(sizeof(double) * 2 * DOT_BLOCKS);
-    hipStream_t st = (hipStream_t)stream;
-    dot(dA, dB, p->nval, 1.0, part.as<double>(), dOut, st);
+    lsdm_pattern* q = const_cast<lsdm_pattern*>(p);
+    {
+      std::lock_guard<std::mutex> lk(q->maps_mutex);
+      if (!q->d_dotpart.p) q->d_dotpart.alloc(sizeof(double) * 2 * DOT_BLOCKS);
+    }
+    dot(dA, dB, p->nval, 1.0, q->d_dotpart.as<double>(), dOut, (hipStream_t)stream);
     check_launch();
-    HIP_CHECK(hipStreamSynchronize(st));
   });
 }
 

@@ -171,6 +171,8 @@ struct lsdm_pattern {
   // (its transpose) into the dropped half, else 0.  Built on first use.
   lsdm::DevBuf d_mirw;
   bool mirw_ready = false;
+  // partial sums of lsdm_dot (allocated on its first call)
+  lsdm::DevBuf d_dotpart;
   std::mutex maps_mutex;
 };
 

@@ -126,6 +126,19 @@ def test_product_adjoint_and_dot():
     assert abs(d - oracle.dot(a, b)) <= 1e-13 * np.sum(np.abs(a * b))
 
 
+def test_dot_calls_queued_back_to_back():
+    """lsdm_dot returns without waiting and reuses the pattern's partial
+    sums: dots queued one after another on a stream each give their own
+    oracle value."""
+    s = workloads.diamond(2, jitter=0.1, seed=4)
+    gs = lsdm.System.from_workload(s)
+    gp, op = lsdm.Pattern(gs, 12.0), oracle.pattern(s, 12.0)
+    pairs = [(_rand(op, 10 + 2 * k), _rand(op, 11 + 2 * k)) for k in range(4)]
+    outs = [lsdm.dot(gp, T(a), T(b)) for a, b in pairs]
+    for (a, b), o in zip(pairs, outs):
+        assert abs(o.item() - oracle.dot(a, b)) <= 1e-13 * np.sum(np.abs(a * b))
+
+
 # ---------------------------------------------------------------------------
 # the LNV chain
 # ---------------------------------------------------------------------------
