@@ -63,6 +63,8 @@ class System:
         self._destroy = lib().lsdm_system_destroy
         self.n = xyz.shape[0]
         self.nfn = nfn.copy()
+        self.xyz = xyz.copy()
+        self.lattice = None if lat is None else lat.reshape(3, 3).copy()
 
     @classmethod
     def from_workload(cls, sysm):
@@ -311,3 +313,4 @@ class LNV:
 
 
 from .autograd import LNVEnergy  # noqa: E402
+from .checkpoint import load_checkpoint, save_checkpoint  # noqa: E402
