@@ -295,6 +295,20 @@ def test_caller_allocator_serves_every_workspace():
         lsdm.set_allocator()
 
 
+def test_checkpoint_resume_on_the_device(tmp_path):
+    """A handle and values loaded from a checkpoint onto the GPU give the
+    saved handle's energy and dE/dL bit for bit."""
+    s, rS, rH, rL = CHAIN_CASES["si_slab_h_2x2x2"]()
+    lnv, v = _chain_setup(s, rS, rH, rL, symmetric=True)
+    L, S, H = T(v["L"]), T(v["S"]), T(v["H"])
+    E0, G0 = lnv.energy_grad(L, S, H, prec="fp32")
+    path = tmp_path / "run.npz"
+    lsdm.save_checkpoint(path, lnv, {"L": L, "S": S, "H": H})
+    lnv2, vals = lsdm.load_checkpoint(path, device=DEV)
+    E1, G1 = lnv2.energy_grad(vals["L"], vals["S"], vals["H"], prec="fp32")
+    assert torch.equal(E0, E1) and torch.equal(G0, G1)
+
+
 def test_autograd_function():
     s, rS, rH, rL = CHAIN_CASES["si64_jitter_rl16"]()
     lnv, v = _chain_setup(s, rS, rH, rL)
