@@ -142,7 +142,10 @@ _allocators = []   # every pair ever set stays alive: buffers keep the allocator
 def set_allocator(alloc=None, release=None):
     """Route the library's device workspaces through alloc(nbytes) -> device
     pointer (int; None or 0 for failure) and release(ptr) (lsdm_set_allocator);
-    no arguments restores hipMalloc."""
+    no arguments restores hipMalloc.  Handles made while a pair is set give
+    their workspaces back through it when destroyed, so destroy them before
+    the interpreter shuts down (the pair's Python functions may be gone by
+    then)."""
     if (alloc is None) != (release is None):
         raise ValueError("set_allocator needs both alloc and release, or neither")
     if alloc is None:
