@@ -179,7 +179,8 @@ int lsdm_multiply_adjoint(const lsdm_plan* plan, int prec, const double* dCbar, 
  * pattern; Tr(AB) for symmetric B).  FP64 with per-thread compensated sums and
  * a fixed-order tree, so the result is bitwise reproducible.  dOut: device.
  * Returns without waiting; its partial sums live on the pattern (16 KiB,
- * allocated on the first call), so later calls allocate nothing. */
+ * allocated on the first call), so later calls allocate nothing.
+ * Errors: LSDM_EINVAL (null argument), LSDM_ENOMEM, LSDM_EDEVICE. */
 int lsdm_dot(const lsdm_pattern* p, const double* dA, const double* dB, double* dOut, void* stream);
 /* lsdm_dot without allocation, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
@@ -194,7 +195,8 @@ int lsdm_dot_noalloc(const lsdm_pattern* p, const double* dA, const double* dB, 
 
 /* ---- the LNV chain ------------------------------------------------------- */
 /* Patterns of S (range rS), H (rH) and L (rL) plus the intermediates
- * X = LS (rL + rS), M = LSL (min(2 rL + rS, rH + rL + rS)) and every plan of
+ * X = LS (the blocks that L S reaches, all within rL + rS), M = LSL
+ * (min(2 rL + rS, rH + rL + rS)) and every plan of
  * the forward and adjoint chains.  These ranges drop only elements that cannot
  * reach K on H's range or dE/dL on L's range, so E and dE/dL equal the
  * untruncated algebra restricted to the S, H and L patterns.  Any ranges are
@@ -207,7 +209,8 @@ enum {
   /* Symmetric inputs (section 2: S and H of a real basis, and L built like K,
    * are symmetric: block (j,i,-n) = block (i,j,n)^T).  M = LSL, P = LSLSL and
    * dE/dL are then symmetric too.  The products X L and X M compute one half
-   * of their output strips and the other half is filled with transposes, and
+   * of their output strips; the other half is the transpose of the first
+   * (X L's epilogue writes it, the other consumers read the mirror blocks), and
    * the adjoint takes dE/dL as V + V^T - 4 X^T H X with X = LS and
    * V = 6 HX - 4 HMS (the same terms as the gradient of eq. 3, regrouped;
    * HX formed once on M's range and reused for both terms, X^T H X on one
